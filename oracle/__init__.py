@@ -1,0 +1,136 @@
+"""CPU oracle for windowed median/MAD RFI excision -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+may import this package.  The product path (the HIP library and its Python
+binding) never does, and shares no code with it.
+
+The arithmetic lives in ``rfi_oracle.c`` (plain C, full sort per window);
+this module only builds it with gcc and marshals numpy arrays through ctypes.
+Paper: Buch et al., "Implementing and Characterizing Real-time Broadband RFI
+Excision for the GMRT Wideband Backend", Sec. II-D, Eqs. (1)-(2).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rfi_oracle.c")
+_LIB = os.path.join(_HERE, "librfi_oracle.so")
+
+ZERO, CLIP, NOISE = 0, 1, 2
+
+STATS_DTYPE = np.dtype(
+    [("median", "<i4"), ("mad", "<i4"), ("n_flagged", "<u4"), ("threshold", "<f4")]
+)
+
+
+def build() -> str:
+    """Compile the oracle with gcc (binary32 on SSE, no contraction)."""
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-pthread",
+           "-o", _LIB, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        L.orc_philox4x64_10.argtypes = [P, P, P]
+        L.orc_philox4x64_10.restype = None
+        L.orc_q8_table.argtypes = [P]
+        L.orc_q8_table.restype = None
+        L.orc_layout.argtypes = [ctypes.c_int32, P, P, P, P]
+        L.orc_layout.restype = ctypes.c_int64
+        for name in ("orc_window_i8", "orc_window_i16"):
+            f = getattr(L, name)
+            f.argtypes = [P, P, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                          ctypes.c_uint64, ctypes.c_float, ctypes.c_int32, P]
+            f.restype = None
+        for name in ("orc_filter_i8", "orc_filter_i16"):
+            f = getattr(L, name)
+            f.argtypes = [P, P, ctypes.c_int32, P, P, P, P, ctypes.c_uint64, P,
+                          ctypes.c_int32]
+            f.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def philox4x64_10(ctr, key) -> list[int]:
+    """One Philox4x64-10 block for a 4-word counter and a 2-word key."""
+    c = np.array([int(v) for v in ctr], dtype=np.uint64)
+    k = np.array([int(v) for v in key], dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    lib().orc_philox4x64_10(_ptr(c), _ptr(k), _ptr(out))
+    return [int(v) for v in out]
+
+
+def q8_table() -> np.ndarray:
+    out = np.zeros(4096, dtype=np.int16)
+    lib().orc_q8_table(_ptr(out))
+    return out
+
+
+def layout(lengths, windows):
+    """(sample_offsets, window_offsets, total_windows) of the packed layout."""
+    L = np.ascontiguousarray(lengths, dtype=np.int64)
+    W = np.ascontiguousarray(windows, dtype=np.int32)
+    so = np.zeros(len(L), dtype=np.int64)
+    wo = np.zeros(len(L), dtype=np.int64)
+    total = lib().orc_layout(len(L), _ptr(L), _ptr(W), _ptr(so), _ptr(wo))
+    return so, wo, int(total)
+
+
+def window(x, k: float, mode: int, *, abs_start: int = 0, stream: int = 0, seed: int = 0):
+    """Filter one window; returns (y, stats) with stats a STATS_DTYPE scalar record."""
+    x = np.ascontiguousarray(x)
+    if x.dtype == np.int8:
+        f = lib().orc_window_i8
+    elif x.dtype == np.int16:
+        f = lib().orc_window_i16
+    else:
+        raise TypeError("oracle windows are int8 or int16")
+    y = np.empty_like(x)
+    st = np.zeros(1, dtype=STATS_DTYPE)
+    f(_ptr(x), _ptr(y), len(x), abs_start, stream, seed, float(k), int(mode), _ptr(st))
+    return y, st[0]
+
+
+def filter_batch(x, lengths, windows, k, mode, seed: int = 0, n_threads: int | None = None):
+    """Whole packed batch; returns (y, stats[total_windows]).
+
+    Padding elements of y (between streams) are copied from x, as the oracle
+    never writes them.
+    """
+    x = np.ascontiguousarray(x)
+    n = len(lengths)
+    L = np.ascontiguousarray(lengths, dtype=np.int64)
+    W = np.ascontiguousarray(windows, dtype=np.int32)
+    K = np.ascontiguousarray(np.broadcast_to(np.asarray(k, dtype=np.float32), (n,)))
+    M = np.ascontiguousarray(np.broadcast_to(np.asarray(mode, dtype=np.int32), (n,)))
+    _, _, total = layout(L, W)
+    if total < 0:
+        raise ValueError("invalid lengths/windows")
+    y = x.copy()
+    st = np.zeros(max(total, 1), dtype=STATS_DTYPE)
+    f = lib().orc_filter_i8 if x.dtype == np.int8 else lib().orc_filter_i16
+    if n_threads is None:
+        n_threads = os.cpu_count() or 1
+    rc = f(_ptr(x), _ptr(y), n, _ptr(L), _ptr(W), _ptr(K), _ptr(M), seed, _ptr(st), n_threads)
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return y, st[:total]
