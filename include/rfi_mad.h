@@ -1,0 +1,228 @@
+/*
+ * rfi_mad.h -- C ABI of librfimad, MI355X (gfx950) windowed median/MAD
+ * broadband RFI excision.
+ *
+ * The method (Buch et al., "Implementing and Characterizing Real-time
+ * Broadband RFI Excision for the GMRT Wideband Backend", Sec. II-D):
+ * each input's time series is cut into non-overlapping windows; per window
+ * the median M(x) and the median absolute deviation D are found, the
+ * thresholds of Eq. (1) are M(x) +/- n * (1.4826 * D) (the multiple n is the
+ * argument `k` here), and Eq. (2) replaces every sample outside them.
+ *
+ * Conventions fixed by this library (where the paper is silent):
+ *   - windows are contiguous, aligned at sample 0 of each stream, and a
+ *     short final window is a window of its own;
+ *   - median = lower median, the sample of rank floor((N-1)/2) in sorted
+ *     order; MAD = the same rank of |x - median|;
+ *   - t = k * (1.4826f * (float)D), two IEEE binary32 round-to-nearest
+ *     multiplies; a sample is flagged iff |x - median| > t (strict);
+ *   - replacements (`mode`):
+ *       RFI_MODE_ZERO   0
+ *       RFI_MODE_CLIP   median +/- floor(t) on the sample's side, saturated
+ *       RFI_MODE_NOISE  saturate(median + q), q = (s * G[u] + 2^15) >> 16
+ *                       (arithmetic shift), s = (int)(1.4826f*D * 256.0f),
+ *                       G[u] = round(256 * PhiInv((u + 0.5) / 4096)),
+ *                       u = top 12 bits of word (j & 3) of the
+ *                       Philox4x64-10 block (Salmon et al., SC'11) with
+ *                       key (seed, stream) and counter (j >> 2, 0, 0, 0),
+ *                       j = absolute sample index within the stream.
+ *   - statistics are taken from the input window in every mode.
+ *
+ * Packed layout used by every batch entry point:
+ *   stream s occupies elements [off_s, off_s + L_s) of x and y, with
+ *   off_s = sum_{j<s} align_up(L_j, 64); the buffers must hold at least
+ *   off_{n-1} + align_up(L_{n-1}, 64) elements.  Elements between streams
+ *   (padding) are read but never written.  Window w of stream s writes
+ *   stats[woff_s + w], woff_s = sum_{j<s} ceil(L_j / W_j).  rfi_layout()
+ *   computes both offset arrays.
+ *
+ * Ownership and threading: x, y, stats are caller-owned device memory that
+ * must stay valid until the enqueued work has run on `stream`; the host
+ * arrays (lengths, windows, k, mode) are read during the call only.  All
+ * work is asynchronous on `stream` (a hipStream_t; NULL = the null stream).
+ * y == x (exactly in place) is allowed; any other overlap is rejected.
+ * Errors: every entry point returns an rfi_status; nothing is enqueued when
+ * it is not RFI_OK.  Device faults surface at the caller's synchronisation.
+ */
+#ifndef RFI_MAD_H
+#define RFI_MAD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RFI_OK = 0,
+    RFI_ERR_INVALID = -1,     /* bad argument value or size                  */
+    RFI_ERR_ALIGN = -2,       /* x, y or stats not 16-byte aligned           */
+    RFI_ERR_UNSUPPORTED = -3, /* valid request this build cannot serve       */
+    RFI_ERR_NOMEM = -4,       /* device or host allocation failed            */
+    RFI_ERR_HIP = -5,         /* a HIP runtime call failed (see status text) */
+    RFI_ERR_BUSY = -6         /* serving: admission refused (budget/slots)   */
+} rfi_status;
+
+typedef enum { RFI_MODE_ZERO = 0, RFI_MODE_CLIP = 1, RFI_MODE_NOISE = 2 } rfi_mode;
+
+/* Per-window statistics, 16 bytes, computed from the input window. */
+typedef struct {
+    int32_t median;     /* lower median M(x)                          */
+    int32_t mad;        /* D = median |x - M(x)|                      */
+    uint32_t n_flagged; /* samples with |x - M(x)| > threshold        */
+    float threshold;    /* t = k * (1.4826f * D), binary32            */
+} rfi_window_stats;
+
+/* Limits checked by rfi_validate. */
+#define RFI_MAX_WINDOW 65536
+#define RFI_MAX_K 1.0e4f
+
+/* ------------------------------------------------------------------ */
+/* Batch filtering (Sec. II-D, Eqs. (1)-(2)).                          */
+/* ------------------------------------------------------------------ */
+
+/* Filter n_streams packed int8 streams.
+ *   x, y      device pointers, 16-byte aligned, packed layout above.
+ *   lengths   host array [n_streams], L_s >= 0 samples.
+ *   windows   host array [n_streams], 1 <= W_s <= RFI_MAX_WINDOW.
+ *   k         host array [n_streams], finite, 0 <= k <= RFI_MAX_K.
+ *   mode      host array [n_streams], rfi_mode values.
+ *   seed      Philox key word 0 for NOISE replacement.
+ *   stats_out device pointer [total windows] or NULL (no statistics).
+ *   stream    hipStream_t (NULL = null stream).
+ * Plans (work tables) are cached per distinct argument signature. */
+int rfi_mad_filter(const int8_t* x, int8_t* y, int32_t n_streams, const int64_t* lengths,
+                   const int32_t* windows, const float* k, const int32_t* mode, uint64_t seed,
+                   rfi_window_stats* stats_out, void* stream);
+
+/* Same for int16 samples (radix-select median and MAD). */
+int rfi_mad_filter_i16(const int16_t* x, int16_t* y, int32_t n_streams, const int64_t* lengths,
+                       const int32_t* windows, const float* k, const int32_t* mode, uint64_t seed,
+                       rfi_window_stats* stats_out, void* stream);
+
+/* Layout helper (host only): fills sample_offsets[n] and window_offsets[n]
+ * (either may be NULL) and returns the total number of windows, or
+ * RFI_ERR_INVALID.  The element count the buffers need is returned in
+ * *total_elems when that pointer is not NULL. */
+int64_t rfi_layout(int32_t n_streams, const int64_t* lengths, const int32_t* windows,
+                   int64_t* sample_offsets, int64_t* window_offsets, int64_t* total_elems);
+
+/* Argument check of rfi_mad_filter[_i16] without touching the device
+ * (host only).  elem_size is 1 (int8) or 2 (int16). */
+int rfi_validate(int32_t elem_size, const void* x, const void* y, int32_t n_streams,
+                 const int64_t* lengths, const int32_t* windows, const float* k,
+                 const int32_t* mode, const void* stats_out);
+
+/* Static text for a status code; for RFI_ERR_HIP, the last HIP error seen
+ * by this thread. */
+const char* rfi_status_string(int status);
+
+/* Version string of the library build. */
+const char* rfi_version(void);
+
+/* ------------------------------------------------------------------ */
+/* Explicit plans: a work table for one argument signature, reusable   */
+/* across calls, with a selectable launch schedule and HIP-graph       */
+/* replay.  rfi_mad_filter uses the same machinery through a cache.    */
+/* ------------------------------------------------------------------ */
+typedef struct rfi_plan rfi_plan;
+
+typedef enum {
+    RFI_SCHED_AUTO = 0,        /* autotuned table, else RFI_SCHED_SPLIT         */
+    RFI_SCHED_SPLIT = 1,       /* one launch per window class, one WG per tile  */
+    RFI_SCHED_SPLIT_PERSIST = 2, /* one persistent launch per window class     */
+    RFI_SCHED_FUSED = 3,       /* one persistent launch for every class         */
+    RFI_SCHED_PER_STREAM = 4,  /* one ordinary launch per stream (baseline)     */
+    RFI_SCHED_COUNT = 5
+} rfi_schedule;
+
+/* elem_size 1 or 2; arrays as in rfi_mad_filter.  Allocates device work
+ * tables (hipMalloc) and copies them synchronously. */
+int rfi_plan_create(int32_t elem_size, int32_t n_streams, const int64_t* lengths,
+                    const int32_t* windows, const float* k, const int32_t* mode, uint64_t seed,
+                    rfi_plan** out);
+int rfi_plan_set_schedule(rfi_plan* plan, int32_t schedule);
+int rfi_plan_get_schedule(const rfi_plan* plan);
+/* use_graph != 0: capture the launches into a HIP graph on first use with a
+ * given (x, y, stats, stream) and replay it afterwards (not on the null
+ * stream, where launches are direct). */
+int rfi_plan_set_graph(rfi_plan* plan, int32_t use_graph);
+int rfi_plan_execute(rfi_plan* plan, const void* x, void* y, rfi_window_stats* stats_out,
+                     void* stream);
+/* Number of kernel launches one execute makes, and total windows. */
+int rfi_plan_info(const rfi_plan* plan, int32_t* n_launches, int64_t* n_windows,
+                  int64_t* n_tiles, int64_t* n_generic);
+/* Time every schedule on the given buffers (iters executes each, median
+ * per schedule), select the fastest and report it and its time (ms).
+ * Writes y and stats. */
+int rfi_plan_autotune(rfi_plan* plan, const void* x, void* y, rfi_window_stats* stats_out,
+                      void* stream, int32_t iters, int32_t* best_schedule, float* best_ms);
+int rfi_plan_destroy(rfi_plan* plan);
+
+/* Drop cached plans and graphs (all devices of this process). */
+int rfi_shutdown(void);
+
+/* ------------------------------------------------------------------ */
+/* Serving: blocks of many streams arrive over time; each stream keeps */
+/* its carry (the samples of an unfinished window) and absolute index  */
+/* on the device; blocks are admitted against an HBM budget and filled */
+/* into shared batched launches (continuous batching).                 */
+/* Output of a stream is emitted window by window: a submit emits the  */
+/* carry plus as many whole windows as the block completes, into       */
+/* out_dev, which must hold n + W - 1 elements.                        */
+/* ------------------------------------------------------------------ */
+typedef struct rfi_server rfi_server;
+
+typedef struct {
+    int32_t elem_size;          /* 1 (int8) or 2 (int16)                     */
+    int32_t max_streams;        /* stream ids are 0 .. max_streams-1          */
+    int32_t max_inflight;       /* blocks admitted but not yet completed      */
+    int32_t max_batch;          /* blocks per launch                          */
+    uint64_t hbm_budget_bytes;  /* in+out bytes of admitted, unfinished blocks */
+    uint64_t seed;              /* Philox key word 0                          */
+    int32_t n_lanes;            /* HIP streams used for overlapping batches   */
+    int32_t schedule;           /* rfi_schedule for the batch launches        */
+} rfi_server_config;
+
+int rfi_server_create(const rfi_server_config* cfg, rfi_server** out);
+/* Register stream `stream_id` with its window, threshold multiple and
+ * replacement mode (the Philox key word 1 is stream_id). */
+int rfi_server_add_stream(rfi_server* srv, uint32_t stream_id, int32_t window, float k,
+                          int32_t mode);
+/* Admit one block of n samples of stream_id (block_dev: device memory of
+ * n elements, 16-byte aligned, valid until the ticket completes).  Output
+ * goes to out_dev (n + W - 1 elements), stats of the emitted windows to
+ * stats_dev (ceil((n + W - 1) / W) entries, may be NULL).  Returns
+ * RFI_ERR_BUSY when the budget or the in-flight limit is reached. */
+int rfi_server_submit(rfi_server* srv, uint32_t stream_id, const void* block_dev, void* out_dev,
+                      int64_t n, rfi_window_stats* stats_dev, uint64_t* ticket);
+/* Launch whatever admitted blocks are not yet on the device (one batched
+ * launch per max_batch blocks).  Called by submit when a batch fills. */
+int rfi_server_dispatch(rfi_server* srv);
+/* done = 1 once the ticket's block has been filtered; samples_emitted and
+ * windows_emitted report what its out/stats buffers received. */
+int rfi_server_poll(rfi_server* srv, uint64_t ticket, int32_t* done, int64_t* samples_emitted,
+                    int64_t* windows_emitted);
+/* Block until every admitted block has completed. */
+int rfi_server_sync(rfi_server* srv);
+/* End of stream: filter the carry as a short final window into out_dev
+ * (W - 1 elements) / stats_dev (1 entry); *n_out receives its length. */
+int rfi_server_flush(rfi_server* srv, uint32_t stream_id, void* out_dev,
+                     rfi_window_stats* stats_dev, int64_t* n_out);
+/* Carry state of one stream, for checkpoint/restore: absolute index of
+ * the next sample, carry length, and the carry samples (host buffer of
+ * at least W - 1 elements). */
+int rfi_server_snapshot(rfi_server* srv, uint32_t stream_id, int64_t* next_index,
+                        int32_t* carry_len, void* carry_host);
+int rfi_server_restore(rfi_server* srv, uint32_t stream_id, int64_t next_index,
+                       int32_t carry_len, const void* carry_host);
+/* Counters: admitted, refused (BUSY), completed, launches. */
+int rfi_server_counters(const rfi_server* srv, uint64_t* admitted, uint64_t* refused,
+                        uint64_t* completed, uint64_t* launches);
+int rfi_server_destroy(rfi_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RFI_MAD_H */

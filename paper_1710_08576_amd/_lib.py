@@ -1,0 +1,232 @@
+"""ctypes binding of librfimad (argument marshalling only).
+
+Every filtering step runs in the HIP library; this module only turns torch
+tensors into pointers and Python sequences into host arrays.  There is no
+fallback: if the library or a HIP device is missing the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librfimad.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "rfi_mad.h")
+
+RFI_OK = 0
+STATUS = {0: "RFI_OK", -1: "RFI_ERR_INVALID", -2: "RFI_ERR_ALIGN", -3: "RFI_ERR_UNSUPPORTED",
+          -4: "RFI_ERR_NOMEM", -5: "RFI_ERR_HIP", -6: "RFI_ERR_BUSY"}
+ZERO, CLIP, NOISE = 0, 1, 2
+SCHED_AUTO, SCHED_SPLIT, SCHED_SPLIT_PERSIST, SCHED_FUSED, SCHED_PER_STREAM = range(5)
+SCHEDULES = {"auto": 0, "split": 1, "split_persist": 2, "fused": 3, "per_stream": 4}
+
+STATS_DTYPE = np.dtype(
+    [("median", "<i4"), ("mad", "<i4"), ("n_flagged", "<u4"), ("threshold", "<f4")]
+)
+
+
+class RfiError(RuntimeError):
+    def __init__(self, status: int, where: str, text: str = ""):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)} ({text})")
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("elem_size", ctypes.c_int32), ("max_streams", ctypes.c_int32),
+                ("max_inflight", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("hbm_budget_bytes", ctypes.c_uint64), ("seed", ctypes.c_uint64),
+                ("n_lanes", ctypes.c_int32), ("schedule", ctypes.c_int32)]
+
+
+_lib = None
+P = ctypes.c_void_p
+I32, I64, U32, U64, F32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_float
+PP = ctypes.POINTER(ctypes.c_void_p)
+
+_SIGS = {
+    "rfi_mad_filter": (ctypes.c_int, [P, P, I32, P, P, P, P, U64, P, P]),
+    "rfi_mad_filter_i16": (ctypes.c_int, [P, P, I32, P, P, P, P, U64, P, P]),
+    "rfi_layout": (ctypes.c_int64, [I32, P, P, P, P, P]),
+    "rfi_validate": (ctypes.c_int, [I32, P, P, I32, P, P, P, P, P]),
+    "rfi_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "rfi_version": (ctypes.c_char_p, []),
+    "rfi_plan_create": (ctypes.c_int, [I32, I32, P, P, P, P, U64, PP]),
+    "rfi_plan_set_schedule": (ctypes.c_int, [P, I32]),
+    "rfi_plan_get_schedule": (ctypes.c_int, [P]),
+    "rfi_plan_set_graph": (ctypes.c_int, [P, I32]),
+    "rfi_plan_execute": (ctypes.c_int, [P, P, P, P, P]),
+    "rfi_plan_info": (ctypes.c_int, [P, P, P, P, P]),
+    "rfi_plan_autotune": (ctypes.c_int, [P, P, P, P, P, I32, P, P]),
+    "rfi_plan_destroy": (ctypes.c_int, [P]),
+    "rfi_shutdown": (ctypes.c_int, []),
+    "rfi_server_create": (ctypes.c_int, [P, PP]),
+    "rfi_server_add_stream": (ctypes.c_int, [P, U32, I32, F32, I32]),
+    "rfi_server_submit": (ctypes.c_int, [P, U32, P, P, I64, P, P]),
+    "rfi_server_dispatch": (ctypes.c_int, [P]),
+    "rfi_server_poll": (ctypes.c_int, [P, U64, P, P, P]),
+    "rfi_server_sync": (ctypes.c_int, [P]),
+    "rfi_server_flush": (ctypes.c_int, [P, U32, P, P, P]),
+    "rfi_server_snapshot": (ctypes.c_int, [P, U32, P, P, P]),
+    "rfi_server_restore": (ctypes.c_int, [P, U32, I64, I32, P]),
+    "rfi_server_counters": (ctypes.c_int, [P, P, P, P, P]),
+    "rfi_server_destroy": (ctypes.c_int, [P]),
+}
+
+
+def header_symbols() -> list[str]:
+    """Every function the public header declares."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(rfi_\w+)\s*\(", text, re.M)))
+
+
+def load():
+    """Load librfimad.so (built by build.py).  Raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"librfimad.so not built ({LIB_PATH}); run __graft_entry__.build()")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int, where: str):
+    if rc != RFI_OK:
+        text = load().rfi_status_string(rc)
+        raise RfiError(rc, where, text.decode() if text else "")
+
+
+def _arr(values, dtype, n):
+    a = np.ascontiguousarray(np.broadcast_to(np.asarray(values, dtype=dtype), (n,)))
+    return a
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _tptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def layout(lengths, windows):
+    """(sample_offsets, window_offsets, total_windows, total_elems)."""
+    L = np.ascontiguousarray(lengths, dtype=np.int64)
+    W = _arr(windows, np.int32, len(L))
+    so = np.zeros(len(L), dtype=np.int64)
+    wo = np.zeros(len(L), dtype=np.int64)
+    tot = np.zeros(1, dtype=np.int64)
+    nw = load().rfi_layout(len(L), _ptr(L), _ptr(W), _ptr(so), _ptr(wo), _ptr(tot))
+    if nw < 0:
+        _check(int(nw), "rfi_layout")
+    return so, wo, int(nw), int(tot[0])
+
+
+def validate(elem_size, x_ptr, y_ptr, lengths, windows, k, mode, stats_ptr=0) -> int:
+    n = len(lengths)
+    L = np.ascontiguousarray(lengths, dtype=np.int64)
+    W, K, M = _arr(windows, np.int32, n), _arr(k, np.float32, n), _arr(mode, np.int32, n)
+    return load().rfi_validate(elem_size, P(x_ptr), P(y_ptr), n, _ptr(L), _ptr(W), _ptr(K),
+                               _ptr(M), P(stats_ptr))
+
+
+def stats_numpy(stats_t) -> np.ndarray:
+    """Device stats tensor (int32 [n, 4]) -> numpy structured array."""
+    raw = stats_t.detach().cpu().contiguous().numpy()
+    return raw.view(STATS_DTYPE).reshape(-1)
+
+
+def mad_filter(x, lengths, windows, k, mode, seed: int = 0, y=None, stats=True, stream=None):
+    """Filter packed streams on the device.  x: int8 or int16 CUDA tensor in
+    the packed layout; returns (y, stats) with stats an int32 [n_windows, 4]
+    tensor (median, mad, n_flagged, threshold bits) or None."""
+    import torch
+    n = len(lengths)
+    L = np.ascontiguousarray(lengths, dtype=np.int64)
+    W, K, M = _arr(windows, np.int32, n), _arr(k, np.float32, n), _arr(mode, np.int32, n)
+    _, _, nw, _ = layout(L, W)
+    if y is None:
+        y = torch.empty_like(x)
+    st = torch.empty((max(nw, 1), 4), dtype=torch.int32, device=x.device) if stats else None
+    if x.dtype == torch.int8:
+        f = load().rfi_mad_filter
+    elif x.dtype == torch.int16:
+        f = load().rfi_mad_filter_i16
+    else:
+        raise TypeError("x must be int8 or int16")
+    rc = f(_tptr(x), _tptr(y), n, _ptr(L), _ptr(W), _ptr(K), _ptr(M), seed, _tptr(st),
+           _stream_handle(stream))
+    _check(rc, "rfi_mad_filter")
+    return y, (st[:nw] if st is not None else None)
+
+
+class Plan:
+    """A reusable work table for one argument signature."""
+
+    def __init__(self, elem_size, lengths, windows, k, mode, seed=0):
+        n = len(lengths)
+        self.L = np.ascontiguousarray(lengths, dtype=np.int64)
+        self.W = _arr(windows, np.int32, n)
+        self.K = _arr(k, np.float32, n)
+        self.M = _arr(mode, np.int32, n)
+        self.elem_size = elem_size
+        self.n_windows = layout(self.L, self.W)[2]
+        h = ctypes.c_void_p()
+        _check(load().rfi_plan_create(elem_size, n, _ptr(self.L), _ptr(self.W), _ptr(self.K),
+                                      _ptr(self.M), seed, ctypes.byref(h)), "rfi_plan_create")
+        self.h = h
+
+    def set_schedule(self, sched):
+        if isinstance(sched, str):
+            sched = SCHEDULES[sched]
+        _check(load().rfi_plan_set_schedule(self.h, int(sched)), "rfi_plan_set_schedule")
+
+    def schedule(self) -> int:
+        return load().rfi_plan_get_schedule(self.h)
+
+    def set_graph(self, on: bool):
+        _check(load().rfi_plan_set_graph(self.h, 1 if on else 0), "rfi_plan_set_graph")
+
+    def execute(self, x, y, stats=None, stream=None):
+        _check(load().rfi_plan_execute(self.h, _tptr(x), _tptr(y), _tptr(stats),
+                                       _stream_handle(stream)), "rfi_plan_execute")
+
+    def info(self):
+        nl = np.zeros(1, np.int32)
+        a = np.zeros(3, np.int64)
+        _check(load().rfi_plan_info(self.h, _ptr(nl), _ptr(a[0:1]), _ptr(a[1:2]), _ptr(a[2:3])),
+               "rfi_plan_info")
+        return {"launches": int(nl[0]), "windows": int(a[0]), "tiles": int(a[1]), "generic": int(a[2])}
+
+    def autotune(self, x, y, stats=None, iters=5, stream=None):
+        best = np.zeros(1, np.int32)
+        ms = np.zeros(1, np.float32)
+        _check(load().rfi_plan_autotune(self.h, _tptr(x), _tptr(y), _tptr(stats),
+                                        _stream_handle(stream), iters, _ptr(best), _ptr(ms)),
+               "rfi_plan_autotune")
+        return int(best[0]), float(ms[0])
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().rfi_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

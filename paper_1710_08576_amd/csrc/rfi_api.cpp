@@ -1,0 +1,616 @@
+// rfi_api.cpp -- C ABI of librfimad: argument checks, packed layout, plans
+// (work tables + launch schedules + HIP-graph replay), the autotuner and the
+// cached batch entry points.  Kernels live in rfi_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "rfi_internal.hpp"
+#include "rfi_runtime.hpp"
+
+using namespace rfi;
+
+namespace rfi {
+
+static thread_local hipError_t t_last_hip = hipSuccess;
+
+int hip_fail(hipError_t e)
+{
+    t_last_hip = e;
+    return RFI_ERR_HIP;
+}
+
+static int64_t align64(int64_t n) { return (n + 63) / 64 * 64; }
+
+int validate_values(int elem, int32_t n, const int64_t* L, const int32_t* W, const float* K,
+                    const int32_t* M)
+{
+    if (elem != 1 && elem != 2) return RFI_ERR_INVALID;
+    if (n < 0) return RFI_ERR_INVALID;
+    if (n == 0) return RFI_OK;
+    if (!L || !W || !K || !M) return RFI_ERR_INVALID;
+    for (int32_t s = 0; s < n; ++s) {
+        if (!std::isfinite(K[s]) || K[s] < 0.0f || K[s] > RFI_MAX_K) return RFI_ERR_INVALID;
+        if (M[s] < RFI_MODE_ZERO || M[s] > RFI_MODE_NOISE) return RFI_ERR_INVALID;
+    }
+    if (rfi_layout(n, L, W, nullptr, nullptr, nullptr) < 0) return RFI_ERR_INVALID;
+    return RFI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotune table: schedule chosen for a coarse plan signature.
+// ---------------------------------------------------------------------------
+static std::mutex g_tune_mu;
+static std::map<uint64_t, int> g_tune;
+
+uint64_t plan_signature(const rfi_plan* p);
+
+int tuned_schedule(uint64_t sig)
+{
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find(sig);
+    return it == g_tune.end() ? RFI_SCHED_SPLIT : it->second;
+}
+
+void record_schedule(uint64_t sig, int sched)
+{
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune[sig] = sched;
+}
+
+}  // namespace rfi
+
+// ---------------------------------------------------------------------------
+// Plans.
+// ---------------------------------------------------------------------------
+struct PlanLaunch {
+    int kind;   // 0 tiles of one class, 1 generic, 2 fused
+    int cls;    // tile class for kind 0
+    bool noise; // tile kernel with the noise path
+    int64_t first, count;
+    int grid;
+};
+
+struct GraphEntry {
+    uint64_t x, y, st;
+    hipStream_t s;
+    int sched;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+struct rfi_plan {
+    int elem = 1;
+    int n = 0;
+    int device = 0;
+    uint64_t seed = 0;
+    std::vector<int64_t> L;
+    std::vector<int32_t> W;
+    std::vector<float> K;
+    std::vector<int32_t> M;
+    std::vector<StreamDesc> hdesc;
+    std::vector<Item> hitems;
+    StreamDesc* ddesc = nullptr;
+    Item* ditems = nullptr;
+    int64_t n_windows = 0, n_tiles = 0, n_generic = 0;
+    int schedule = RFI_SCHED_AUTO;
+    int use_graph = 0;
+    std::vector<PlanLaunch> launches[RFI_SCHED_COUNT];
+    std::vector<GraphEntry> graphs;
+};
+
+namespace rfi {
+
+uint64_t plan_signature(const rfi_plan* p)
+{
+    // dtype, window classes present, noise present, generic present
+    uint64_t sig = (uint64_t)p->elem;
+    for (int s = 0; s < p->n; ++s) {
+        const int cls = p->elem == 1 ? i8_tile_class(p->W[s]) : i16_tile_class(p->W[s]);
+        sig |= 1ull << (8 + (cls < 0 ? 15 : cls));
+        if (p->M[s] == RFI_MODE_NOISE) sig |= 1ull << 32;
+    }
+    if (p->n_generic) sig |= 1ull << 33;
+    return sig;
+}
+
+static int tile_class(int elem, int32_t w) { return elem == 1 ? i8_tile_class(w) : i16_tile_class(w); }
+
+static hipError_t run_launch(const rfi_plan* p, const PlanLaunch& l, const LaunchArgs& base,
+                             hipStream_t s)
+{
+    LaunchArgs a = base;
+    a.items = p->ditems + l.first;
+    a.n_items = l.count;
+    if (p->elem == 1) {
+        if (l.kind == 0) return launch_i8_tiles(l.cls, l.noise, a, l.grid, s);
+        if (l.kind == 1) return launch_i8_generic(a, l.grid, s);
+        return launch_i8_fused(a, l.grid, s);
+    }
+    if (l.kind == 0) return launch_i16_tiles(l.cls, a, l.grid, s);
+    if (l.kind == 1) return launch_i16_generic(a, l.grid, s);
+    return launch_i16_fused(a, l.grid, s);
+}
+
+static void build_launches(rfi_plan* p)
+{
+    const int elem = p->elem;
+    const int ncls = elem == 1 ? kI8Classes : kI16Classes;
+    // Items are ordered: generic items, then tiles of class 0, 1, ...; in
+    // each group by stream, then position.  Ranges per group:
+    std::vector<int64_t> gbegin(ncls + 1, 0), gend(ncls + 1, 0);
+    std::vector<bool> gnoise(ncls + 1, false);
+    {
+        int64_t pos = 0;
+        for (int g = 0; g <= ncls; ++g) {
+            gbegin[g] = pos;
+            while (pos < (int64_t)p->hitems.size()) {
+                const Item& it = p->hitems[pos];
+                const int cls = it.kind == kItemGeneric ? -1 : tile_class(elem, p->W[it.stream]);
+                const int grp = cls < 0 ? 0 : cls + 1;
+                if (grp != g) break;
+                if (p->M[it.stream] == RFI_MODE_NOISE) gnoise[g] = true;
+                ++pos;
+            }
+            gend[g] = pos;
+        }
+    }
+    const int64_t n_items = (int64_t)p->hitems.size();
+    auto clamp_grid = [](int64_t c) { return (int)std::min<int64_t>(std::max<int64_t>(c, 1), 1 << 30); };
+    for (int sched = 0; sched < RFI_SCHED_COUNT; ++sched) p->launches[sched].clear();
+    for (int g = 0; g <= ncls; ++g) {
+        const int64_t c = gend[g] - gbegin[g];
+        if (c == 0) continue;
+        const int cls = g - 1;
+        PlanLaunch l{g == 0 ? 1 : 0, cls, (bool)gnoise[g], gbegin[g], c, clamp_grid(c)};
+        p->launches[RFI_SCHED_SPLIT].push_back(l);
+        l.grid = (int)std::min<int64_t>(c, persistent_grid(elem, cls, l.noise, false));
+        p->launches[RFI_SCHED_SPLIT_PERSIST].push_back(l);
+    }
+    if (n_items > 0) {
+        PlanLaunch f{2, -1, true, 0, n_items,
+                     (int)std::min<int64_t>(n_items, persistent_grid(elem, -1, true, true))};
+        p->launches[RFI_SCHED_FUSED].push_back(f);
+    }
+    // One ordinary launch per stream and kind (the plain baseline).
+    for (int s = 0; s < p->n; ++s) {
+        for (int g = 0; g <= ncls; ++g) {
+            int64_t b = -1, e = -1;
+            for (int64_t i = gbegin[g]; i < gend[g]; ++i) {
+                if (p->hitems[i].stream == s) {
+                    if (b < 0) b = i;
+                    e = i + 1;
+                } else if (b >= 0) {
+                    break;
+                }
+            }
+            if (b < 0) continue;
+            PlanLaunch l{g == 0 ? 1 : 0, g - 1, p->M[s] == RFI_MODE_NOISE, b, e - b, clamp_grid(e - b)};
+            p->launches[RFI_SCHED_PER_STREAM].push_back(l);
+        }
+    }
+    p->launches[RFI_SCHED_AUTO] = p->launches[RFI_SCHED_SPLIT];
+}
+
+int plan_build(int elem, int32_t n, const int64_t* L, const int32_t* W, const float* K,
+               const int32_t* M, uint64_t seed, rfi_plan** out)
+{
+    std::unique_ptr<rfi_plan> p(new rfi_plan);
+    p->elem = elem;
+    p->n = n;
+    p->seed = seed;
+    p->L.assign(L, L + n);
+    p->W.assign(W, W + n);
+    p->K.assign(K, K + n);
+    p->M.assign(M, M + n);
+    if (hipGetDevice(&p->device) != hipSuccess) p->device = 0;
+    const int64_t tile_samples = kTileBytes / elem;
+    const int ncls = elem == 1 ? kI8Classes : kI16Classes;
+    std::vector<std::vector<Item>> groups(ncls + 1);
+    int64_t soff = 0, woff = 0;
+    p->hdesc.resize(n);
+    for (int s = 0; s < n; ++s) {
+        StreamDesc& d = p->hdesc[s];
+        std::memset(&d, 0, sizeof(d));
+        d.x_off = (uint64_t)(soff * elem);
+        d.y_off = (uint64_t)(soff * elem);
+        d.stats_off = (uint64_t)(woff * (int64_t)sizeof(rfi_window_stats));
+        d.head_off = 0;
+        d.length = L[s];
+        d.abs_base = 0;
+        d.window = W[s];
+        d.k = K[s];
+        d.mode = M[s];
+        d.key = (uint32_t)s;
+        d.head_len = 0;
+        d.flags = 0;
+        const int64_t nw = (L[s] + W[s] - 1) / W[s];
+        const int cls = tile_class(elem, W[s]);
+        int64_t first_generic = 0;
+        if (cls >= 0) {
+            const int64_t nt = L[s] / tile_samples;
+            for (int64_t t = 0; t < nt; ++t) groups[cls + 1].push_back(Item{s, kItemTile, t * tile_samples});
+            first_generic = nt * (tile_samples / W[s]);
+            p->n_tiles += nt;
+        }
+        for (int64_t w = first_generic; w < nw; ++w) groups[0].push_back(Item{s, kItemGeneric, w});
+        p->n_generic += nw - first_generic;
+        p->n_windows += nw;
+        soff += align64(L[s]);
+        woff += nw;
+    }
+    for (auto& g : groups) p->hitems.insert(p->hitems.end(), g.begin(), g.end());
+    if (n > 0) {
+        hipError_t e = hipMalloc(&p->ddesc, sizeof(StreamDesc) * n);
+        if (e != hipSuccess) return e == hipErrorOutOfMemory ? RFI_ERR_NOMEM : hip_fail(e);
+        e = hipMemcpy(p->ddesc, p->hdesc.data(), sizeof(StreamDesc) * n, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    if (!p->hitems.empty()) {
+        hipError_t e = hipMalloc(&p->ditems, sizeof(Item) * p->hitems.size());
+        if (e != hipSuccess) return e == hipErrorOutOfMemory ? RFI_ERR_NOMEM : hip_fail(e);
+        e = hipMemcpy(p->ditems, p->hitems.data(), sizeof(Item) * p->hitems.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    build_launches(p.get());
+    *out = p.release();
+    return RFI_OK;
+}
+
+static void drop_graphs(rfi_plan* p)
+{
+    for (auto& g : p->graphs) {
+        (void)hipStreamSynchronize(g.s);
+        (void)hipGraphExecDestroy(g.exec);
+        (void)hipGraphDestroy(g.graph);
+    }
+    p->graphs.clear();
+}
+
+void plan_free(rfi_plan* p)
+{
+    if (!p) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(p->device);
+    drop_graphs(p);
+    if (p->ddesc || p->ditems) (void)hipDeviceSynchronize();
+    if (p->ddesc) (void)hipFree(p->ddesc);
+    if (p->ditems) (void)hipFree(p->ditems);
+    (void)hipSetDevice(cur);
+    delete p;
+}
+
+static int effective_schedule(const rfi_plan* p)
+{
+    if (p->schedule != RFI_SCHED_AUTO) return p->schedule;
+    return tuned_schedule(plan_signature(p));
+}
+
+int plan_execute(rfi_plan* p, const void* x, void* y, rfi_window_stats* st, hipStream_t s,
+                 int sched_override)
+{
+    const int sched = sched_override >= 0 ? sched_override : effective_schedule(p);
+    LaunchArgs base;
+    std::memset(&base, 0, sizeof(base));
+    base.streams = p->ddesc;
+    base.seed = p->seed;
+    base.x_base = (uint64_t)(uintptr_t)x;
+    base.y_base = (uint64_t)(uintptr_t)y;
+    base.stats_base = (uint64_t)(uintptr_t)st;
+    base.no_stats = st ? 0 : 1;
+    const auto& ls = p->launches[sched];
+    if (p->use_graph && s != nullptr && !ls.empty()) {
+        for (auto& g : p->graphs) {
+            if (g.x == base.x_base && g.y == base.y_base && g.st == base.stats_base && g.s == s &&
+                g.sched == sched) {
+                hipError_t e = hipGraphLaunch(g.exec, s);
+                return e == hipSuccess ? RFI_OK : hip_fail(e);
+            }
+        }
+        if (p->graphs.size() >= 8) {
+            (void)hipStreamSynchronize(p->graphs.front().s);
+            (void)hipGraphExecDestroy(p->graphs.front().exec);
+            (void)hipGraphDestroy(p->graphs.front().graph);
+            p->graphs.erase(p->graphs.begin());
+        }
+        GraphEntry g{base.x_base, base.y_base, base.stats_base, s, sched, nullptr, nullptr};
+        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e);
+        hipError_t le = hipSuccess;
+        for (const auto& l : ls) {
+            le = run_launch(p, l, base, s);
+            if (le != hipSuccess) break;
+        }
+        e = hipStreamEndCapture(s, &g.graph);
+        if (le != hipSuccess) return hip_fail(le);
+        if (e != hipSuccess) return hip_fail(e);
+        e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g.graph);
+            return hip_fail(e);
+        }
+        p->graphs.push_back(g);
+        e = hipGraphLaunch(g.exec, s);
+        return e == hipSuccess ? RFI_OK : hip_fail(e);
+    }
+    for (const auto& l : ls) {
+        hipError_t e = run_launch(p, l, base, s);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    return RFI_OK;
+}
+
+}  // namespace rfi
+
+// ---------------------------------------------------------------------------
+// C ABI.
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* rfi_status_string(int status)
+{
+    switch (status) {
+        case RFI_OK: return "ok";
+        case RFI_ERR_INVALID: return "invalid argument";
+        case RFI_ERR_ALIGN: return "pointer not 16-byte aligned";
+        case RFI_ERR_UNSUPPORTED: return "unsupported request";
+        case RFI_ERR_NOMEM: return "out of memory";
+        case RFI_ERR_HIP: return hipGetErrorString(t_last_hip);
+        case RFI_ERR_BUSY: return "admission refused: budget or in-flight limit reached";
+        default: return "unknown status";
+    }
+}
+
+const char* rfi_version(void) { return "rfimad 0.1 gfx950"; }
+
+int64_t rfi_layout(int32_t n_streams, const int64_t* lengths, const int32_t* windows,
+                   int64_t* sample_offsets, int64_t* window_offsets, int64_t* total_elems)
+{
+    if (n_streams < 0 || (n_streams > 0 && (!lengths || !windows))) return RFI_ERR_INVALID;
+    int64_t samples = 0, wins = 0;
+    const int64_t kLimit = (int64_t)1 << 61;
+    for (int32_t s = 0; s < n_streams; ++s) {
+        if (lengths[s] < 0 || lengths[s] > kLimit || windows[s] < 1 || windows[s] > RFI_MAX_WINDOW)
+            return RFI_ERR_INVALID;
+        if (sample_offsets) sample_offsets[s] = samples;
+        if (window_offsets) window_offsets[s] = wins;
+        samples += align64(lengths[s]);
+        wins += (lengths[s] + windows[s] - 1) / windows[s];
+        if (samples > kLimit) return RFI_ERR_INVALID;
+    }
+    if (total_elems) *total_elems = samples;
+    return wins;
+}
+
+int rfi_validate(int32_t elem_size, const void* x, const void* y, int32_t n_streams,
+                 const int64_t* lengths, const int32_t* windows, const float* k,
+                 const int32_t* mode, const void* stats_out)
+{
+    int rc = rfi::validate_values(elem_size, n_streams, lengths, windows, k, mode);
+    if (rc != RFI_OK || n_streams == 0) return rc;
+    int64_t total = 0;
+    const int64_t wins = rfi_layout(n_streams, lengths, windows, nullptr, nullptr, &total);
+    if (total == 0) return RFI_OK;
+    if (!x || !y) return RFI_ERR_INVALID;
+    const uintptr_t xa = (uintptr_t)x, ya = (uintptr_t)y, sa = (uintptr_t)stats_out;
+    if ((xa | ya | sa) & 15u) return RFI_ERR_ALIGN;
+    const uintptr_t bytes = (uintptr_t)total * (uintptr_t)elem_size;
+    auto overlap = [](uintptr_t a, uintptr_t an, uintptr_t b, uintptr_t bn) { return a < b + bn && b < a + an; };
+    if (xa != ya && overlap(xa, bytes, ya, bytes)) return RFI_ERR_INVALID;
+    if (stats_out && wins > 0) {
+        const uintptr_t sb = (uintptr_t)wins * sizeof(rfi_window_stats);
+        if (overlap(sa, sb, xa, bytes) || overlap(sa, sb, ya, bytes)) return RFI_ERR_INVALID;
+    }
+    return RFI_OK;
+}
+
+int rfi_plan_create(int32_t elem_size, int32_t n_streams, const int64_t* lengths,
+                    const int32_t* windows, const float* k, const int32_t* mode, uint64_t seed,
+                    rfi_plan** out)
+{
+    if (!out) return RFI_ERR_INVALID;
+    *out = nullptr;
+    // Argument values only: buffers are bound at execute.
+    int rc = rfi::validate_values(elem_size, n_streams, lengths, windows, k, mode);
+    if (rc != RFI_OK) return rc;
+    return plan_build(elem_size, n_streams, lengths, windows, k, mode, seed, out);
+}
+
+int rfi_plan_set_schedule(rfi_plan* plan, int32_t schedule)
+{
+    if (!plan || schedule < 0 || schedule >= RFI_SCHED_COUNT) return RFI_ERR_INVALID;
+    plan->schedule = schedule;
+    return RFI_OK;
+}
+
+int rfi_plan_get_schedule(const rfi_plan* plan)
+{
+    if (!plan) return RFI_ERR_INVALID;
+    return effective_schedule(plan);
+}
+
+int rfi_plan_set_graph(rfi_plan* plan, int32_t use_graph)
+{
+    if (!plan) return RFI_ERR_INVALID;
+    plan->use_graph = use_graph ? 1 : 0;
+    return RFI_OK;
+}
+
+int rfi_plan_execute(rfi_plan* plan, const void* x, void* y, rfi_window_stats* stats_out,
+                     void* stream)
+{
+    if (!plan) return RFI_ERR_INVALID;
+    int rc = rfi_validate(plan->elem, x, y, plan->n, plan->L.data(), plan->W.data(), plan->K.data(),
+                          plan->M.data(), stats_out);
+    if (rc != RFI_OK) return rc;
+    return plan_execute(plan, x, y, stats_out, (hipStream_t)stream, -1);
+}
+
+int rfi_plan_info(const rfi_plan* plan, int32_t* n_launches, int64_t* n_windows, int64_t* n_tiles,
+                  int64_t* n_generic)
+{
+    if (!plan) return RFI_ERR_INVALID;
+    if (n_launches) *n_launches = (int32_t)plan->launches[effective_schedule(plan)].size();
+    if (n_windows) *n_windows = plan->n_windows;
+    if (n_tiles) *n_tiles = plan->n_tiles;
+    if (n_generic) *n_generic = plan->n_generic;
+    return RFI_OK;
+}
+
+int rfi_plan_autotune(rfi_plan* plan, const void* x, void* y, rfi_window_stats* stats_out,
+                      void* stream, int32_t iters, int32_t* best_schedule, float* best_ms)
+{
+    if (!plan || iters < 1) return RFI_ERR_INVALID;
+    int rc = rfi_validate(plan->elem, x, y, plan->n, plan->L.data(), plan->W.data(), plan->K.data(),
+                          plan->M.data(), stats_out);
+    if (rc != RFI_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return hip_fail(hipGetLastError());
+    int best = RFI_SCHED_SPLIT;
+    float best_t = 1e30f;
+    const int cands[] = {RFI_SCHED_SPLIT, RFI_SCHED_SPLIT_PERSIST, RFI_SCHED_FUSED};
+    for (int c : cands) {
+        if (plan->launches[c].empty()) continue;
+        rc = plan_execute(plan, x, y, stats_out, s, c);  // warm-up (graph capture)
+        if (rc != RFI_OK) break;
+        std::vector<float> ts;
+        for (int i = 0; i < iters; ++i) {
+            (void)hipEventRecord(e0, s);
+            rc = plan_execute(plan, x, y, stats_out, s, c);
+            (void)hipEventRecord(e1, s);
+            if (rc != RFI_OK) break;
+            (void)hipEventSynchronize(e1);
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            ts.push_back(ms);
+        }
+        if (rc != RFI_OK) break;
+        std::sort(ts.begin(), ts.end());
+        const float med = ts[ts.size() / 2];
+        if (med < best_t) {
+            best_t = med;
+            best = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != RFI_OK) return rc;
+    plan->schedule = best;
+    record_schedule(plan_signature(plan), best);
+    if (best_schedule) *best_schedule = best;
+    if (best_ms) *best_ms = best_t;
+    return RFI_OK;
+}
+
+int rfi_plan_destroy(rfi_plan* plan)
+{
+    plan_free(plan);
+    return RFI_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Cached batch entry points.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct CacheKey {
+    int elem;
+    int device;
+    uint64_t seed;
+    std::vector<int64_t> L;
+    std::vector<int32_t> W;
+    std::vector<uint32_t> K;  // bit patterns
+    std::vector<int32_t> M;
+    bool operator<(const CacheKey& o) const
+    {
+        if (elem != o.elem) return elem < o.elem;
+        if (device != o.device) return device < o.device;
+        if (seed != o.seed) return seed < o.seed;
+        if (L != o.L) return L < o.L;
+        if (W != o.W) return W < o.W;
+        if (K != o.K) return K < o.K;
+        return M < o.M;
+    }
+};
+
+std::mutex g_cache_mu;
+std::map<CacheKey, rfi_plan*> g_cache;
+std::vector<CacheKey> g_cache_order;
+constexpr size_t kCacheMax = 32;
+
+int cached_filter(int elem, const void* x, void* y, int32_t n, const int64_t* L, const int32_t* W,
+                  const float* K, const int32_t* M, uint64_t seed, rfi_window_stats* st, void* stream)
+{
+    int rc = rfi_validate(elem, x, y, n, L, W, K, M, st);
+    if (rc != RFI_OK) return rc;
+    int64_t total = 0;
+    rfi_layout(n, L, W, nullptr, nullptr, &total);
+    if (n == 0 || total == 0) return RFI_OK;
+    CacheKey key;
+    key.elem = elem;
+    if (hipGetDevice(&key.device) != hipSuccess) key.device = 0;
+    key.seed = seed;
+    key.L.assign(L, L + n);
+    key.W.assign(W, W + n);
+    key.K.resize(n);
+    std::memcpy(key.K.data(), K, sizeof(float) * n);
+    key.M.assign(M, M + n);
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    rfi_plan* p = nullptr;
+    auto it = g_cache.find(key);
+    if (it != g_cache.end()) {
+        p = it->second;
+    } else {
+        if (g_cache.size() >= kCacheMax) {
+            auto old = g_cache.find(g_cache_order.front());
+            rfi::plan_free(old->second);
+            g_cache.erase(old);
+            g_cache_order.erase(g_cache_order.begin());
+        }
+        rc = rfi::plan_build(elem, n, L, W, K, M, seed, &p);
+        if (rc != RFI_OK) return rc;
+        g_cache[key] = p;
+        g_cache_order.push_back(key);
+    }
+    return rfi::plan_execute(p, x, y, st, (hipStream_t)stream, -1);
+}
+
+}  // namespace
+
+extern "C" {
+
+int rfi_mad_filter(const int8_t* x, int8_t* y, int32_t n_streams, const int64_t* lengths,
+                   const int32_t* windows, const float* k, const int32_t* mode, uint64_t seed,
+                   rfi_window_stats* stats_out, void* stream)
+{
+    return cached_filter(1, x, y, n_streams, lengths, windows, k, mode, seed, stats_out, stream);
+}
+
+int rfi_mad_filter_i16(const int16_t* x, int16_t* y, int32_t n_streams, const int64_t* lengths,
+                       const int32_t* windows, const float* k, const int32_t* mode, uint64_t seed,
+                       rfi_window_stats* stats_out, void* stream)
+{
+    return cached_filter(2, x, y, n_streams, lengths, windows, k, mode, seed, stats_out, stream);
+}
+
+int rfi_shutdown(void)
+{
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    for (auto& kv : g_cache) rfi::plan_free(kv.second);
+    g_cache.clear();
+    g_cache_order.clear();
+    return RFI_OK;
+}
+
+}  // extern "C"

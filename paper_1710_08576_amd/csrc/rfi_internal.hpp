@@ -1,0 +1,128 @@
+// rfi_internal.hpp -- structures shared by the host runtime and the kernels
+// of librfimad (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rfi_mad.h"
+
+namespace rfi {
+
+// Samples of one workgroup tile: 16 KiB (4 waves x 64 lanes x 64 bytes).
+constexpr int kTileBytes = 16384;
+constexpr int kBlock = 256;
+
+// Per-stream parameters, resident in device memory for the life of a plan.
+// Addresses are byte offsets added to the base addresses of LaunchArgs, so
+// one table serves any buffers (plans) or holds absolute addresses with
+// zero bases (serving).
+struct StreamDesc {
+    uint64_t x_off;      // first input element
+    uint64_t y_off;      // first output element (logical index 0)
+    uint64_t stats_off;  // stats entry of window 0
+    uint64_t head_off;   // carry samples that precede x (serving)
+    int64_t length;      // logical samples: head_len + body samples
+    int64_t abs_base;    // absolute stream index of logical sample 0
+    int32_t window;      // W
+    float k;             // threshold multiple
+    int32_t mode;        // rfi_mode
+    uint32_t key;        // Philox key word 1 (stream index or stream id)
+    int32_t head_len;    // carry samples at head_off
+    int32_t flags;       // kNoStats
+};
+constexpr int32_t kNoStats = 1;
+
+// A stream as the kernels see it, with addresses resolved.
+struct StreamView {
+    const void* x;
+    void* y;
+    rfi_window_stats* stats;  // NULL: no statistics
+    const void* x_head;
+    int64_t length;
+    int64_t abs_base;
+    int32_t window;
+    float k;
+    int32_t mode;
+    uint32_t key;
+    int32_t head_len;
+};
+
+// One unit of work for a workgroup.
+//   kind == kItemTile:    a 16 KiB tile of whole, aligned windows of a stream
+//                         whose W is a tile class; `first` = first sample.
+//   kind == kItemGeneric: one window of any size/alignment; `first` = its
+//                         window index.
+struct Item {
+    int32_t stream;
+    int32_t kind;
+    int64_t first;
+};
+constexpr int32_t kItemTile = 0;
+constexpr int32_t kItemGeneric = 1;
+
+// Window classes with a register-resident tile path.
+//   int8:  512, 1024, 2048, 4096 (one wave per window or less),
+//          8192, 16384 (2 or 4 waves per window);
+//   int16: 8192 (four waves per window).
+inline __host__ __device__ int i8_tile_class(int32_t w)
+{
+    switch (w) {
+        case 512: return 0;
+        case 1024: return 1;
+        case 2048: return 2;
+        case 4096: return 3;
+        case 8192: return 4;
+        case 16384: return 5;
+        default: return -1;
+    }
+}
+constexpr int kI8Classes = 6;
+inline __host__ __device__ int i16_tile_class(int32_t w) { return w == 8192 ? 0 : -1; }
+constexpr int kI16Classes = 1;
+
+// Kernel launch requests issued by the host runtime.
+struct LaunchArgs {
+    const StreamDesc* streams;
+    const Item* items;
+    int64_t n_items;
+    uint64_t seed;
+    uint64_t x_base;      // added to StreamDesc::x_off / head_off
+    uint64_t y_base;      // added to StreamDesc::y_off
+    uint64_t stats_base;  // added to StreamDesc::stats_off
+    int32_t no_stats;     // 1: write no statistics at all
+    int32_t pad;
+};
+
+__host__ __device__ inline StreamView resolve(const StreamDesc& d, const LaunchArgs& a)
+{
+    StreamView v;
+    v.x = reinterpret_cast<const void*>(static_cast<uintptr_t>(a.x_base + d.x_off));
+    v.y = reinterpret_cast<void*>(static_cast<uintptr_t>(a.y_base + d.y_off));
+    v.stats = (a.no_stats || (d.flags & kNoStats))
+                  ? nullptr
+                  : reinterpret_cast<rfi_window_stats*>(static_cast<uintptr_t>(a.stats_base + d.stats_off));
+    v.x_head = reinterpret_cast<const void*>(static_cast<uintptr_t>(a.x_base + d.head_off));
+    v.length = d.length;
+    v.abs_base = d.abs_base;
+    v.window = d.window;
+    v.k = d.k;
+    v.mode = d.mode;
+    v.key = d.key;
+    v.head_len = d.head_len;
+    return v;
+}
+
+// Host wrappers around the kernels (defined in rfi_kernels.hip).
+// cls: tile class (-1 = generic items); fused: one kernel for all kinds.
+hipError_t launch_i8_tiles(int cls, bool noise, const LaunchArgs& a, int grid, hipStream_t s);
+hipError_t launch_i8_generic(const LaunchArgs& a, int grid, hipStream_t s);
+hipError_t launch_i8_fused(const LaunchArgs& a, int grid, hipStream_t s);
+hipError_t launch_i16_tiles(int cls, const LaunchArgs& a, int grid, hipStream_t s);
+hipError_t launch_i16_generic(const LaunchArgs& a, int grid, hipStream_t s);
+hipError_t launch_i16_fused(const LaunchArgs& a, int grid, hipStream_t s);
+
+// Occupancy-derived persistent grid size for a kernel choice.
+int persistent_grid(int elem_size, int cls, bool noise, bool fused);
+
+}  // namespace rfi

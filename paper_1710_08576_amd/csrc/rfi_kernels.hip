@@ -1,0 +1,854 @@
+// rfi_kernels.hip -- gfx950 kernels of librfimad.
+//
+// Method (Buch et al., Sec. II-D): per non-overlapping window, the median
+// M(x), the MAD D, the thresholds M(x) +/- k * (1.4826 * D) of Eq. (1) and the
+// replacement of Eq. (2).  The work is a pure stream: every sample is read
+// once from HBM and written once, so the kernels are built around 128-bit
+// coalesced loads into registers and keep all per-window work in LDS.
+//
+// int8 windows: one 256-bin LDS histogram of x + 128 per window; a
+//   segmented wave scan turns it into cumulative counts C[v]; the median is
+//   the first bin with C >= r + 1 (r = floor((N-1)/2)); the MAD is the first
+//   d with C[m+d] - C[m-d-1] >= r + 1, i.e. the |x - m| histogram folded out
+//   of the same counts, so the samples are histogrammed once.  The flag
+//   count is N - (C[hi] - C[lo-1]) and needs no extra pass.
+// int16 windows: two-digit (8+8 bit) radix select, once for the median on
+//   x + 32768 and once for the MAD on |x - m|.
+// Replacement: the per-sample test |x - m| > t equals x < m - floor(t) or
+//   x > m + floor(t) because |x - m| is an integer, so after one binary32
+//   threshold per window everything is integer; int8 samples are clamped
+//   four to a dword with packed 16-bit max/min.
+// Noise: flagged dwords of a wave are compacted into a list, every lane
+//   draws one Philox4x64-10 block per list entry, and the owners merge the
+//   noise bytes back, so the cost follows the number of flagged dwords, not
+//   the worst lane.
+#include "rfi_device.hpp"
+#include "rfi_internal.hpp"
+
+namespace rfi {
+
+__constant__ int16_t c_q8[4096] = {
+#include "q8_table.inc"
+};
+
+struct WinParams {
+    int32_t lo;   // lowest unflagged value, m - floor(t) saturated
+    int32_t hi;   // highest unflagged value, m + floor(t) saturated
+    int32_t m;    // median
+    int32_t sq8;  // (int)(1.4826f * D * 256), Q8 robust sigma for noise
+};
+
+__device__ __forceinline__ uint64_t pick4(const Philox4x64& r, int i)
+{
+    const uint64_t a = (i & 1) ? r.w[1] : r.w[0];
+    const uint64_t b = (i & 1) ? r.w[3] : r.w[2];
+    return (i & 2) ? b : a;
+}
+
+// Robust sigma, threshold and the integer bounds of one window (Eq. (1)).
+__device__ __forceinline__ float threshold_of(int D, float k, float& sig)
+{
+    sig = __fmul_rn(1.4826f, (float)D);
+    return __fmul_rn(k, sig);
+}
+
+// ---------------------------------------------------------------------------
+// int8: selection from a 256-bin histogram owned by an aligned group of G
+// lanes (G = 8..64, 256 / G bins per lane).  On return the bins hold
+// inclusive cumulative counts and every lane of the group has mb (median
+// + 128) and D.
+// ---------------------------------------------------------------------------
+template <int G>
+__device__ __forceinline__ void select_i8(uint32_t* hw, uint32_t need, int& mb, int& D)
+{
+    constexpr int BPL = 256 / G;
+    const int sl = lane_id() & (G - 1);
+    uint32_t* my = hw + sl * BPL;
+    uint32_t c[BPL];
+#pragma unroll
+    for (int j = 0; j < BPL; j += 4) {
+        const uint4 t = *reinterpret_cast<const uint4*>(my + j);
+        c[j] = t.x;
+        c[j + 1] = t.y;
+        c[j + 2] = t.z;
+        c[j + 3] = t.w;
+    }
+#pragma unroll
+    for (int j = 1; j < BPL; ++j) c[j] += c[j - 1];
+    const uint32_t incl = group_incl_scan<G>(c[BPL - 1]);
+    const uint32_t excl = incl - c[BPL - 1];
+#pragma unroll
+    for (int j = 0; j < BPL; ++j) c[j] += excl;
+#pragma unroll
+    for (int j = 0; j < BPL; j += 4)
+        *reinterpret_cast<uint4*>(my + j) = make_uint4(c[j], c[j + 1], c[j + 2], c[j + 3]);
+    int below = 0;
+#pragma unroll
+    for (int j = 0; j < BPL; ++j) below += (c[j] < need) ? 1 : 0;
+    mb = group_min<G>(below < BPL ? sl * BPL + below : 256);
+    wave_sync();
+    // #{|x - m| <= d} = C[min(mb + d, 255)] - C[mb - d - 1] is non-decreasing in d.
+    int dbelow = 0;
+#pragma unroll
+    for (int j = 0; j < BPL; ++j) {
+        const int d = sl * BPL + j;
+        const int up = min(mb + d, 255);
+        const int dn = mb - d - 1;
+        const uint32_t lowc = dn >= 0 ? hw[max(dn, 0)] : 0u;
+        dbelow += (hw[up] - lowc < need) ? 1 : 0;
+    }
+    D = group_min<G>(dbelow < BPL ? sl * BPL + dbelow : 256);
+}
+
+// Window parameters and statistics from the cumulative histogram hw.
+__device__ __forceinline__ void params_i8(const uint32_t* hw, int mb, int D, float k, int n,
+                                          WinParams& p, rfi_window_stats& s)
+{
+    float sig;
+    const float t = threshold_of(D, k, sig);
+    const int T = (int)floorf(t);
+    const int m = mb - 128;
+    const int lo = max(m - T, -128), hi = min(m + T, 127);
+    const int lob = lo + 128, hib = hi + 128;
+    const uint32_t inside = hw[hib] - (lob > 0 ? hw[max(lob - 1, 0)] : 0u);
+    p.lo = lo;
+    p.hi = hi;
+    p.m = m;
+    p.sq8 = (int)__fmul_rn(sig, 256.0f);
+    s.median = m;
+    s.mad = D;
+    s.n_flagged = (uint32_t)n - inside;
+    s.threshold = t;
+}
+
+// ---------------------------------------------------------------------------
+// Noise for flagged dwords of one wave (16 dwords per lane, bit q of `fl`
+// marks dword q).  The owner lanes publish (lane, q) entries; each lane
+// draws the noise dword of entries lane, lane + 64, ...; owners merge.
+// dword_noise(owner, q) returns the packed replacement dword; mask_of(q)
+// returns the byte/half mask of flagged samples in v[q].
+// scratch: 512 words of LDS private to this wave.
+// ---------------------------------------------------------------------------
+template <class NoiseFn, class MaskFn>
+__device__ __forceinline__ void merge_noise(uint32_t (&v)[16], uint32_t fl, uint32_t* scratch,
+                                            NoiseFn dword_noise, MaskFn mask_of)
+{
+    const int lane = lane_id();
+    uint32_t* list = scratch;
+    uint32_t* stage = scratch + 256;
+    const uint32_t cnt = __popc(fl);
+    const uint32_t incl = group_incl_scan<64>(cnt);
+    const int base = (int)(incl - cnt);
+    const int F = (int)__shfl(incl, 63);
+    for (int r0 = 0; r0 < F; r0 += 256) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int e = base + __popc(fl & ((1u << q) - 1u)) - r0;
+            if (((fl >> q) & 1u) && e >= 0 && e < 256) list[e] = (uint32_t)(lane << 4 | q);
+        }
+        wave_sync();
+        const int nE = min(256, F - r0);
+        for (int e = lane; e < nE; e += 64) {
+            const uint32_t ent = list[e];
+            stage[e] = dword_noise((int)(ent >> 4), (int)(ent & 15u));
+        }
+        wave_sync();
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int e = base + __popc(fl & ((1u << q) - 1u)) - r0;
+            if (((fl >> q) & 1u) && e >= 0 && e < 256) {
+                const uint32_t mk = mask_of(q);
+                v[q] = (v[q] & ~mk) | (stage[e] & mk);
+            }
+        }
+        wave_sync();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// int8 tile: 16 KiB of whole windows of one class W, 64 bytes per lane.
+// ---------------------------------------------------------------------------
+template <int W, bool NOISE>
+struct I8TileSmem {
+    static constexpr int kWin = 16384 / W;
+    uint32_t hist[kWin * 256];
+    WinParams prm[kWin];
+    uint32_t noise[NOISE ? 4 * 512 : 1];
+};
+
+template <int W, bool NOISE>
+__device__ __forceinline__ void i8_tile(const StreamView& d, int64_t first, uint64_t seed,
+                                        I8TileSmem<W, NOISE>& sm)
+{
+    constexpr int NWW = W < 4096 ? 4096 / W : 1;  // windows per wave
+    constexpr int WPW = W > 4096 ? W / 4096 : 1;  // waves per window
+    constexpr int G = 64 / NWW;                   // lanes per window in the scan
+    const int lane = lane_id();
+    const int wave = (int)(threadIdx.x >> 6);
+    const int wbase = wave * 4096;
+    const uint8_t* xt = static_cast<const uint8_t*>(d.x) + first + wbase + lane * 16;
+    uint8_t* yt = static_cast<uint8_t*>(d.y) + first + wbase + lane * 16;
+
+    uint32_t v[16];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint4 t = *reinterpret_cast<const uint4*>(xt + i * 1024);
+        v[4 * i] = t.x;
+        v[4 * i + 1] = t.y;
+        v[4 * i + 2] = t.z;
+        v[4 * i + 3] = t.w;
+    }
+
+    // Zero the histograms this wave (or workgroup) owns.
+    if constexpr (WPW == 1) {
+        uint4* h = reinterpret_cast<uint4*>(sm.hist + wave * NWW * 256);
+#pragma unroll
+        for (int j = 0; j < NWW; ++j) h[j * 64 + lane] = make_uint4(0, 0, 0, 0);
+        wave_sync();
+    } else {
+        __syncthreads();
+        if (threadIdx.x < (16384 / W) * 64)
+            reinterpret_cast<uint4*>(sm.hist)[threadIdx.x] = make_uint4(0, 0, 0, 0);
+        __syncthreads();
+    }
+
+    // Histogram of x + 128 (the byte xor 0x80).
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        uint32_t* h = sm.hist + ((wbase + i * 1024 + lane * 16) / W) * 256;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t u = v[4 * i + j] ^ 0x80808080u;
+            atomicAdd(&h[u & 0xFFu], 1u);
+            atomicAdd(&h[(u >> 8) & 0xFFu], 1u);
+            atomicAdd(&h[(u >> 16) & 0xFFu], 1u);
+            atomicAdd(&h[u >> 24], 1u);
+        }
+    }
+
+    constexpr uint32_t need = (W - 1) / 2 + 1;
+    if constexpr (WPW == 1) {
+        wave_sync();
+        const int wl = wave * NWW + lane / G;
+        uint32_t* hw = sm.hist + wl * 256;
+        int mb, D;
+        select_i8<G>(hw, need, mb, D);
+        WinParams p;
+        rfi_window_stats s;
+        params_i8(hw, mb, D, d.k, W, p, s);
+        if ((lane & (G - 1)) == 0) {
+            sm.prm[wl] = p;
+            if (d.stats) d.stats[first / W + wl] = s;
+        }
+        wave_sync();
+    } else {
+        __syncthreads();
+        if (wave % WPW == 0) {
+            const int wl = wave / WPW;
+            uint32_t* hw = sm.hist + wl * 256;
+            int mb, D;
+            select_i8<64>(hw, need, mb, D);
+            WinParams p;
+            rfi_window_stats s;
+            params_i8(hw, mb, D, d.k, W, p, s);
+            if (lane == 0) {
+                sm.prm[wl] = p;
+                if (d.stats) d.stats[first / W + wl] = s;
+            }
+        }
+        __syncthreads();
+    }
+
+    // Replacement (Eq. (2)).
+    const int mode = d.mode;
+    if (mode == RFI_MODE_CLIP) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const WinParams p = sm.prm[(wbase + i * 1024 + lane * 16) / W];
+            const uint32_t lo = rep_i16(p.lo * 256), hi = rep_i16(p.hi * 256);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[4 * i + j] = clamp_i8x4(v[4 * i + j], lo, hi);
+        }
+    } else if (!NOISE || mode == RFI_MODE_ZERO) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const WinParams p = sm.prm[(wbase + i * 1024 + lane * 16) / W];
+            const uint32_t lo = rep_i16(p.lo * 256), hi = rep_i16(p.hi * 256);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t x = v[4 * i + j];
+                v[4 * i + j] = x & ~nonzero_byte_mask(clamp_i8x4(x, lo, hi) ^ x);
+            }
+        }
+    } else if constexpr (NOISE) {
+        uint32_t fl = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const WinParams p = sm.prm[(wbase + i * 1024 + lane * 16) / W];
+            const uint32_t lo = rep_i16(p.lo * 256), hi = rep_i16(p.hi * 256);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t x = v[4 * i + j];
+                fl |= (clamp_i8x4(x, lo, hi) != x ? 1u : 0u) << (4 * i + j);
+            }
+        }
+        const int64_t abs0 = d.abs_base + first + wbase;
+        const uint64_t key1 = d.key;
+        auto noise = [&](int owner, int q) -> uint32_t {
+            const int off = (q >> 2) * 1024 + owner * 16 + (q & 3) * 4;
+            const WinParams p = sm.prm[(wbase + off) / W];
+            const Philox4x64 r = philox4x64_10((uint64_t)(abs0 + off) >> 2, seed, key1);
+            uint32_t out = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int g = c_q8[(uint32_t)(r.w[b] >> 52)];
+                const int q8 = (p.sq8 * g + 32768) >> 16;
+                out |= ((uint32_t)min(max(p.m + q8, -128), 127) & 0xFFu) << (8 * b);
+            }
+            return out;
+        };
+        // Each dword is merged once, so v[q] still holds the input when
+        // its mask is taken.
+        auto mask = [&](int q) -> uint32_t {
+            const WinParams p = sm.prm[(wbase + (q >> 2) * 1024 + lane * 16) / W];
+            const uint32_t x = v[q];
+            return nonzero_byte_mask(clamp_i8x4(x, rep_i16(p.lo * 256), rep_i16(p.hi * 256)) ^ x);
+        };
+        merge_noise(v, fl, sm.noise + wave * 512, noise, mask);
+    }
+
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        *reinterpret_cast<uint4*>(yt + i * 1024) =
+            make_uint4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]);
+}
+
+// ---------------------------------------------------------------------------
+// int8 generic window: any length, any alignment, optional head segment.
+// One workgroup per window; two passes over the samples in global memory.
+// ---------------------------------------------------------------------------
+struct GenericSmem {
+    uint32_t hist[4 * 256];  // int16 radix uses four digit histograms
+    WinParams prm;
+    int32_t sel[4];
+    uint32_t flagged;
+};
+
+template <typename T>
+__device__ __forceinline__ int load_logical(const StreamView& d, int64_t i)
+{
+    return i < d.head_len ? (int)static_cast<const T*>(d.x_head)[i]
+                          : (int)static_cast<const T*>(d.x)[i - d.head_len];
+}
+
+__device__ __forceinline__ int noise_sample(int64_t j, uint64_t seed, uint32_t key, int m, int sq8,
+                                            int vmin, int vmax)
+{
+    const Philox4x64 r = philox4x64_10((uint64_t)j >> 2, seed, key);
+    const int g = c_q8[(uint32_t)(pick4(r, (int)(j & 3)) >> 52)];
+    const int64_t q = ((int64_t)sq8 * g + 32768) >> 16;
+    return (int)min(max((int64_t)m + q, (int64_t)vmin), (int64_t)vmax);
+}
+
+__device__ void i8_generic(const StreamView& d, int64_t w, uint64_t seed, GenericSmem& sm)
+{
+    const int W = d.window;
+    const int64_t a = w * (int64_t)W;
+    const int n = (int)min((int64_t)W, d.length - a);
+    const int tid = (int)threadIdx.x;
+    int8_t* y = static_cast<int8_t*>(d.y);
+    __syncthreads();
+    sm.hist[tid] = 0;
+    __syncthreads();
+    for (int i = tid; i < n; i += kBlock) atomicAdd(&sm.hist[load_logical<int8_t>(d, a + i) + 128], 1u);
+    __syncthreads();
+    if (tid < 64) {
+        int mb, D;
+        select_i8<64>(sm.hist, (uint32_t)((n - 1) / 2 + 1), mb, D);
+        WinParams p;
+        rfi_window_stats s;
+        params_i8(sm.hist, mb, D, d.k, n, p, s);
+        if (tid == 0) {
+            sm.prm = p;
+            if (d.stats) d.stats[w] = s;
+        }
+    }
+    __syncthreads();
+    const WinParams p = sm.prm;
+    for (int i = tid; i < n; i += kBlock) {
+        const int x = load_logical<int8_t>(d, a + i);
+        int yv = x;
+        if (x < p.lo || x > p.hi) {
+            if (d.mode == RFI_MODE_ZERO) yv = 0;
+            else if (d.mode == RFI_MODE_CLIP) yv = min(max(x, p.lo), p.hi);
+            else yv = noise_sample(d.abs_base + a + i, seed, d.key, p.m, p.sq8, -128, 127);
+        }
+        y[a + i] = (int8_t)yv;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// int16: radix select over two 8-bit digits.
+// ---------------------------------------------------------------------------
+// Find the bucket of rank `need` (1-based) in a 256-bin histogram whose bins
+// are spread over R replicas (bin b, replica r at b * R + r).  Every lane of
+// the wave gets the bucket and the count below it.  hw is left unchanged.
+template <int R>
+__device__ __forceinline__ void bucket_of(const uint32_t* hw, uint32_t need, int& bucket,
+                                          uint32_t& below)
+{
+    const int lane = lane_id();
+    uint32_t c[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t* src = hw + (lane * 4 + j) * R;
+        uint32_t s = 0;
+        if constexpr (R >= 4) {
+#pragma unroll
+            for (int r = 0; r < R; r += 4) {
+                const uint4 t = *reinterpret_cast<const uint4*>(src + r);
+                s += t.x + t.y + t.z + t.w;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) s += src[r];
+        }
+        c[j] = s;
+    }
+#pragma unroll
+    for (int j = 1; j < 4; ++j) c[j] += c[j - 1];
+    const uint32_t incl = group_incl_scan<64>(c[3]);
+    const uint32_t excl = incl - c[3];
+    int nb = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) nb += (c[j] + excl < need) ? 1 : 0;
+    // lane holding the bucket: first lane with nb < 4
+    const int cand = nb < 4 ? lane * 4 + nb : 255;
+    bucket = group_min<64>(cand);  // 255 if the histogram held fewer than `need`
+    // count below the bucket: cumulative count of bucket - 1
+    const int src_lane = (bucket - 1) >> 2, src_j = (bucket - 1) & 3;
+    uint32_t mine = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if (j == src_j) mine = c[j] + excl;
+    const uint32_t got = __shfl(mine, max(src_lane, 0));
+    below = bucket > 0 ? got : 0u;
+}
+
+__device__ __forceinline__ void zero_words(uint32_t* p, int words, int tid, int nthreads)
+{
+    for (int i = tid * 4; i < words; i += nthreads * 4)
+        *reinterpret_cast<uint4*>(p + i) = make_uint4(0, 0, 0, 0);
+}
+
+struct I16TileSmem {
+    static constexpr int R = 8;
+    uint32_t h1[256 * R];  // high digit of x + 32768
+    uint32_t h2[256];      // low digit of x + 32768 inside the median bucket
+    uint32_t h3[256 * R];  // high digit of |x - m|
+    uint32_t h4[256];      // low digit of |x - m| inside the MAD bucket
+    uint32_t flagged;
+    uint32_t noise[4 * 512];
+};
+
+__device__ __forceinline__ int lo16(uint32_t v) { return (int)(int16_t)(v & 0xFFFFu); }
+__device__ __forceinline__ int hi16(uint32_t v) { return (int)(int16_t)(v >> 16); }
+
+// W = 8192 int16 samples = 16 KiB = one window per workgroup tile.
+__device__ void i16_tile_8192(const StreamView& d, int64_t first, uint64_t seed, I16TileSmem& sm)
+{
+    constexpr int W = 8192;
+    constexpr int R = I16TileSmem::R;
+    const int lane = lane_id();
+    const int wave = (int)(threadIdx.x >> 6);
+    const int tid = (int)threadIdx.x;
+    const int wbase = wave * 4096;  // bytes
+    const uint8_t* xt = reinterpret_cast<const uint8_t*>(static_cast<const int16_t*>(d.x) + first) + wbase + lane * 16;
+    uint8_t* yt = reinterpret_cast<uint8_t*>(static_cast<int16_t*>(d.y) + first) + wbase + lane * 16;
+
+    uint32_t v[16];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint4 t = *reinterpret_cast<const uint4*>(xt + i * 1024);
+        v[4 * i] = t.x;
+        v[4 * i + 1] = t.y;
+        v[4 * i + 2] = t.z;
+        v[4 * i + 3] = t.w;
+    }
+    __syncthreads();
+    zero_words(sm.h1, 256 * R, tid, kBlock);
+    zero_words(sm.h3, 256 * R, tid, kBlock);
+    zero_words(sm.h2, 256, tid, kBlock);
+    zero_words(sm.h4, 256, tid, kBlock);
+    if (tid == 0) sm.flagged = 0;
+    __syncthreads();
+
+    const int rep = lane & (R - 1);
+    // Digit 1 of x + 32768.
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const uint32_t u = v[q] ^ 0x80008000u;
+        atomicAdd(&sm.h1[((u >> 8) & 0xFFu) * R + rep], 1u);
+        atomicAdd(&sm.h1[(u >> 24) * R + rep], 1u);
+    }
+    __syncthreads();
+    constexpr uint32_t need = (W - 1) / 2 + 1;
+    int b1;
+    uint32_t below1;
+    bucket_of<R>(sm.h1, need, b1, below1);
+    // Digit 2 inside bucket b1.
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const uint32_t u = v[q] ^ 0x80008000u;
+        if ((int)((u >> 8) & 0xFFu) == b1) atomicAdd(&sm.h2[u & 0xFFu], 1u);
+        if ((int)(u >> 24) == b1) atomicAdd(&sm.h2[(u >> 16) & 0xFFu], 1u);
+    }
+    __syncthreads();
+    int b2;
+    uint32_t below2;
+    bucket_of<1>(sm.h2, need - below1, b2, below2);
+    const int m = ((b1 << 8) | b2) - 32768;
+    // Digits of |x - m| in [0, 65535].
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const uint32_t d0 = (uint32_t)abs(lo16(v[q]) - m), d1 = (uint32_t)abs(hi16(v[q]) - m);
+        atomicAdd(&sm.h3[(d0 >> 8) * R + rep], 1u);
+        atomicAdd(&sm.h3[(d1 >> 8) * R + rep], 1u);
+    }
+    __syncthreads();
+    int b3;
+    uint32_t below3;
+    bucket_of<R>(sm.h3, need, b3, below3);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const uint32_t d0 = (uint32_t)abs(lo16(v[q]) - m), d1 = (uint32_t)abs(hi16(v[q]) - m);
+        if ((int)(d0 >> 8) == b3) atomicAdd(&sm.h4[d0 & 0xFFu], 1u);
+        if ((int)(d1 >> 8) == b3) atomicAdd(&sm.h4[d1 & 0xFFu], 1u);
+    }
+    __syncthreads();
+    int b4;
+    uint32_t below4;
+    bucket_of<1>(sm.h4, need - below3, b4, below4);
+    const int D = (b3 << 8) | b4;
+
+    float sig;
+    const float t = threshold_of(D, d.k, sig);
+    const int T = (int)floorf(t);
+    const int lo = max(m - T, -32768), hi = min(m + T, 32767);
+    const uint32_t lo2 = rep_i16(lo), hi2 = rep_i16(hi);
+    const int sq8 = (int)__fmul_rn(sig, 256.0f);
+    const int mode = d.mode;
+    uint32_t nflag = 0;
+    uint32_t fl = 0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const uint32_t x = v[q];
+        const uint32_t c = pk_clamp_i16(x, lo2, hi2);
+        const uint32_t mk = nonzero_half_mask(c ^ x);
+        nflag += __popc(mk) >> 4;
+        fl |= (mk != 0 ? 1u : 0u) << q;
+        if (mode == RFI_MODE_CLIP) v[q] = c;
+        else if (mode == RFI_MODE_ZERO) v[q] = x & ~mk;
+    }
+    if (mode == RFI_MODE_NOISE) {
+        const int64_t abs0 = d.abs_base + first + wbase / 2;
+        const uint64_t key1 = d.key;
+        auto noise = [&](int owner, int q) -> uint32_t {
+            const int off = (q >> 2) * 512 + owner * 8 + (q & 3) * 2;  // samples
+            const int64_t j = abs0 + off;
+            const Philox4x64 r = philox4x64_10((uint64_t)j >> 2, seed, key1);
+            uint32_t out = 0;
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int g = c_q8[(uint32_t)(pick4(r, (int)((j + b) & 3)) >> 52)];
+                const int64_t q8 = ((int64_t)sq8 * g + 32768) >> 16;
+                const int val = (int)min(max((int64_t)m + q8, (int64_t)-32768), (int64_t)32767);
+                out |= ((uint32_t)val & 0xFFFFu) << (16 * b);
+            }
+            return out;
+        };
+        auto mask = [&](int q) -> uint32_t {
+            return nonzero_half_mask(pk_clamp_i16(v[q], lo2, hi2) ^ v[q]);
+        };
+        merge_noise(v, fl, sm.noise + wave * 512, noise, mask);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        *reinterpret_cast<uint4*>(yt + i * 1024) =
+            make_uint4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]);
+    nflag = group_sum<64>(nflag);
+    if (lane == 0) atomicAdd(&sm.flagged, nflag);
+    __syncthreads();
+    if (tid == 0 && d.stats) {
+        rfi_window_stats s;
+        s.median = m;
+        s.mad = D;
+        s.n_flagged = sm.flagged;
+        s.threshold = t;
+        d.stats[first / W] = s;
+    }
+}
+
+// Generic int16 window: radix passes over global memory.
+__device__ void i16_generic(const StreamView& d, int64_t w, uint64_t seed, GenericSmem& sm)
+{
+    const int W = d.window;
+    const int64_t a = w * (int64_t)W;
+    const int n = (int)min((int64_t)W, d.length - a);
+    const int tid = (int)threadIdx.x;
+    int16_t* y = static_cast<int16_t*>(d.y);
+    uint32_t* h = sm.hist;
+    const uint32_t need = (uint32_t)((n - 1) / 2 + 1);
+    __syncthreads();
+    for (int i = tid; i < 4 * 256; i += kBlock) h[i] = 0;
+    if (tid == 0) sm.flagged = 0;
+    __syncthreads();
+    for (int i = tid; i < n; i += kBlock)
+        atomicAdd(&h[(uint32_t)(load_logical<int16_t>(d, a + i) + 32768) >> 8], 1u);
+    __syncthreads();
+    if (tid < 64) {
+        int b;
+        uint32_t below;
+        bucket_of<1>(h, need, b, below);
+        if (tid == 0) {
+            sm.sel[0] = b;
+            sm.sel[1] = (int)below;
+        }
+    }
+    __syncthreads();
+    const int b1 = sm.sel[0];
+    const uint32_t below1 = (uint32_t)sm.sel[1];
+    for (int i = tid; i < n; i += kBlock) {
+        const uint32_t u = (uint32_t)(load_logical<int16_t>(d, a + i) + 32768);
+        if ((int)(u >> 8) == b1) atomicAdd(&h[256 + (u & 0xFFu)], 1u);
+    }
+    __syncthreads();
+    if (tid < 64) {
+        int b;
+        uint32_t below;
+        bucket_of<1>(h + 256, need - below1, b, below);
+        if (tid == 0) sm.sel[2] = ((b1 << 8) | b) - 32768;
+    }
+    __syncthreads();
+    const int m = sm.sel[2];
+    for (int i = tid; i < n; i += kBlock) {
+        const uint32_t dv = (uint32_t)abs(load_logical<int16_t>(d, a + i) - m);
+        atomicAdd(&h[512 + (dv >> 8)], 1u);
+    }
+    __syncthreads();
+    if (tid < 64) {
+        int b;
+        uint32_t below;
+        bucket_of<1>(h + 512, need, b, below);
+        if (tid == 0) {
+            sm.sel[0] = b;
+            sm.sel[1] = (int)below;
+        }
+    }
+    __syncthreads();
+    const int b3 = sm.sel[0];
+    const uint32_t below3 = (uint32_t)sm.sel[1];
+    for (int i = tid; i < n; i += kBlock) {
+        const uint32_t dv = (uint32_t)abs(load_logical<int16_t>(d, a + i) - m);
+        if ((int)(dv >> 8) == b3) atomicAdd(&h[768 + (dv & 0xFFu)], 1u);
+    }
+    __syncthreads();
+    if (tid < 64) {
+        int b;
+        uint32_t below;
+        bucket_of<1>(h + 768, need - below3, b, below);
+        if (tid == 0) sm.sel[3] = (b3 << 8) | b;
+    }
+    __syncthreads();
+    const int D = sm.sel[3];
+    float sig;
+    const float t = threshold_of(D, d.k, sig);
+    const int T = (int)floorf(t);
+    const int lo = max(m - T, -32768), hi = min(m + T, 32767);
+    const int sq8 = (int)__fmul_rn(sig, 256.0f);
+    uint32_t nflag = 0;
+    for (int i = tid; i < n; i += kBlock) {
+        const int x = load_logical<int16_t>(d, a + i);
+        int yv = x;
+        if (x < lo || x > hi) {
+            ++nflag;
+            if (d.mode == RFI_MODE_ZERO) yv = 0;
+            else if (d.mode == RFI_MODE_CLIP) yv = min(max(x, lo), hi);
+            else yv = noise_sample(d.abs_base + a + i, seed, d.key, m, sq8, -32768, 32767);
+        }
+        y[a + i] = (int16_t)yv;
+    }
+    nflag = group_sum<64>(nflag);
+    if (lane_id() == 0) atomicAdd(&sm.flagged, nflag);
+    __syncthreads();
+    if (tid == 0 && d.stats) {
+        rfi_window_stats s;
+        s.median = m;
+        s.mad = D;
+        s.n_flagged = sm.flagged;
+        s.threshold = t;
+        d.stats[w] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Kernels.  All loop over items with a grid stride, so the same kernel
+// serves one-workgroup-per-item launches and persistent launches.
+// ---------------------------------------------------------------------------
+template <int CLS, bool NOISE>
+__global__ __launch_bounds__(kBlock) void k_i8_tiles(LaunchArgs a)
+{
+    constexpr int W = 512 << CLS;
+    __shared__ I8TileSmem<W, NOISE> sm;
+    for (int64_t it = blockIdx.x; it < a.n_items; it += gridDim.x) {
+        const Item item = a.items[it];
+        const StreamView d = resolve(a.streams[item.stream], a);
+        i8_tile<W, NOISE>(d, item.first, a.seed, sm);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_i8_generic(LaunchArgs a)
+{
+    __shared__ GenericSmem sm;
+    for (int64_t it = blockIdx.x; it < a.n_items; it += gridDim.x) {
+        const Item item = a.items[it];
+        const StreamView d = resolve(a.streams[item.stream], a);
+        i8_generic(d, item.first, a.seed, sm);
+    }
+}
+
+union I8FusedSmem {
+    I8TileSmem<512, true> c0;
+    I8TileSmem<1024, true> c1;
+    I8TileSmem<2048, true> c2;
+    I8TileSmem<4096, true> c3;
+    I8TileSmem<8192, true> c4;
+    I8TileSmem<16384, true> c5;
+    GenericSmem g;
+};
+
+__global__ __launch_bounds__(kBlock) void k_i8_fused(LaunchArgs a)
+{
+    __shared__ I8FusedSmem sm;
+    for (int64_t it = blockIdx.x; it < a.n_items; it += gridDim.x) {
+        const Item item = a.items[it];
+        const StreamView d = resolve(a.streams[item.stream], a);
+        if (item.kind == kItemGeneric) {
+            i8_generic(d, item.first, a.seed, sm.g);
+            continue;
+        }
+        // Items of different classes may follow each other: keep the LDS
+        // of the previous item alive until every wave is done with it.
+        __syncthreads();
+        switch (i8_tile_class(d.window)) {
+            case 0: i8_tile<512, true>(d, item.first, a.seed, sm.c0); break;
+            case 1: i8_tile<1024, true>(d, item.first, a.seed, sm.c1); break;
+            case 2: i8_tile<2048, true>(d, item.first, a.seed, sm.c2); break;
+            case 3: i8_tile<4096, true>(d, item.first, a.seed, sm.c3); break;
+            case 4: i8_tile<8192, true>(d, item.first, a.seed, sm.c4); break;
+            default: i8_tile<16384, true>(d, item.first, a.seed, sm.c5); break;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_i16_tiles(LaunchArgs a)
+{
+    __shared__ I16TileSmem sm;
+    for (int64_t it = blockIdx.x; it < a.n_items; it += gridDim.x) {
+        const Item item = a.items[it];
+        const StreamView d = resolve(a.streams[item.stream], a);
+        i16_tile_8192(d, item.first, a.seed, sm);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_i16_generic(LaunchArgs a)
+{
+    __shared__ GenericSmem sm;
+    for (int64_t it = blockIdx.x; it < a.n_items; it += gridDim.x) {
+        const Item item = a.items[it];
+        const StreamView d = resolve(a.streams[item.stream], a);
+        i16_generic(d, item.first, a.seed, sm);
+    }
+}
+
+union I16FusedSmem {
+    I16TileSmem t;
+    GenericSmem g;
+};
+
+__global__ __launch_bounds__(kBlock) void k_i16_fused(LaunchArgs a)
+{
+    __shared__ I16FusedSmem sm;
+    for (int64_t it = blockIdx.x; it < a.n_items; it += gridDim.x) {
+        const Item item = a.items[it];
+        const StreamView d = resolve(a.streams[item.stream], a);
+        if (item.kind == kItemGeneric) i16_generic(d, item.first, a.seed, sm.g);
+        else i16_tile_8192(d, item.first, a.seed, sm.t);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host launch wrappers.
+// ---------------------------------------------------------------------------
+static hipError_t launch(void (*k)(LaunchArgs), const LaunchArgs& a, int grid, hipStream_t s)
+{
+    if (a.n_items <= 0) return hipSuccess;
+    if (grid < 1) grid = 1;
+    LaunchArgs args = a;
+    void* kargs[] = {&args};
+    return hipLaunchKernel(reinterpret_cast<const void*>(k), dim3(grid), dim3(kBlock), kargs, 0, s);
+}
+
+template <bool NOISE>
+static void (*i8_tile_kernel(int cls))(LaunchArgs)
+{
+    switch (cls) {
+        case 0: return k_i8_tiles<0, NOISE>;
+        case 1: return k_i8_tiles<1, NOISE>;
+        case 2: return k_i8_tiles<2, NOISE>;
+        case 3: return k_i8_tiles<3, NOISE>;
+        case 4: return k_i8_tiles<4, NOISE>;
+        case 5: return k_i8_tiles<5, NOISE>;
+        default: return nullptr;
+    }
+}
+
+hipError_t launch_i8_tiles(int cls, bool noise, const LaunchArgs& a, int grid, hipStream_t s)
+{
+    auto k = noise ? i8_tile_kernel<true>(cls) : i8_tile_kernel<false>(cls);
+    if (!k) return hipErrorInvalidValue;
+    return launch(k, a, grid, s);
+}
+hipError_t launch_i8_generic(const LaunchArgs& a, int grid, hipStream_t s) { return launch(k_i8_generic, a, grid, s); }
+hipError_t launch_i8_fused(const LaunchArgs& a, int grid, hipStream_t s) { return launch(k_i8_fused, a, grid, s); }
+hipError_t launch_i16_tiles(int cls, const LaunchArgs& a, int grid, hipStream_t s)
+{
+    if (cls != 0) return hipErrorInvalidValue;
+    return launch(k_i16_tiles, a, grid, s);
+}
+hipError_t launch_i16_generic(const LaunchArgs& a, int grid, hipStream_t s) { return launch(k_i16_generic, a, grid, s); }
+hipError_t launch_i16_fused(const LaunchArgs& a, int grid, hipStream_t s) { return launch(k_i16_fused, a, grid, s); }
+
+int persistent_grid(int elem_size, int cls, bool noise, bool fused)
+{
+    void (*k)(LaunchArgs) = nullptr;
+    if (elem_size == 1) {
+        if (fused) k = k_i8_fused;
+        else if (cls < 0) k = k_i8_generic;
+        else k = noise ? i8_tile_kernel<true>(cls) : i8_tile_kernel<false>(cls);
+    } else {
+        if (fused) k = k_i16_fused;
+        else if (cls < 0) k = k_i16_generic;
+        else k = k_i16_tiles;
+    }
+    int per_cu = 0;
+    if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kBlock, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        cus = 256;
+    return per_cu * cus;
+}
+
+}  // namespace rfi

@@ -1,0 +1,88 @@
+"""Host-only checks of the C ABI (no GPU): the library loads, exports every
+function its header declares, and its pure-host calls behave."""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1710_08576_amd as rfi
+from paper_1710_08576_amd import _lib
+
+
+def test_exports_every_declared_symbol():
+    lib = rfi.load()
+    declared = _lib.header_symbols()
+    assert len(declared) >= 20
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(declared) == set(_lib._SIGS), "binding and header disagree"
+
+
+def test_version_and_status_strings():
+    lib = rfi.load()
+    assert b"gfx950" in lib.rfi_version()
+    for code in (0, -1, -2, -3, -4, -6):
+        assert lib.rfi_status_string(code)
+
+
+def test_layout_matches_oracle():
+    rng = np.random.default_rng(0)
+    for _ in range(50):
+        n = int(rng.integers(1, 40))
+        L = rng.integers(0, 100000, n)
+        W = rng.integers(1, 65537, n)
+        so, wo, nw, total = rfi.layout(L, W)
+        so2, wo2, nw2 = oracle.layout(L, W)
+        assert np.array_equal(so, so2) and np.array_equal(wo, wo2) and nw == nw2
+        assert total == int(so[-1]) + (int(L[-1]) + 63) // 64 * 64
+
+
+def test_layout_rejects():
+    lib = rfi.load()
+    L = np.array([10], np.int64)
+    for W in (0, 65537, -3):
+        Wa = np.array([W], np.int32)
+        assert lib.rfi_layout(1, L.ctypes.data, Wa.ctypes.data, None, None, None) == -1
+    Lb = np.array([-1], np.int64)
+    Wa = np.array([4], np.int32)
+    assert lib.rfi_layout(1, Lb.ctypes.data, Wa.ctypes.data, None, None, None) == -1
+
+
+def test_validate():
+    base = 1 << 20  # pretend device addresses: validate never dereferences
+    ok = dict(elem_size=1, x_ptr=base, y_ptr=base + (1 << 16), lengths=[4096, 100],
+              windows=[4096, 10], k=[3.0, 2.5], mode=[0, 2])
+    assert _lib.validate(**ok) == 0
+    assert _lib.validate(**{**ok, "y_ptr": ok["x_ptr"]}) == 0  # in place
+    assert _lib.validate(**{**ok, "x_ptr": base + 1}) == -2
+    assert _lib.validate(**{**ok, "y_ptr": base + 16}) == -1  # partial overlap
+    assert _lib.validate(**{**ok, "k": [3.0, math.inf]}) == -1
+    assert _lib.validate(**{**ok, "k": [3.0, 1e4 + 1]}) == -1
+    assert _lib.validate(**{**ok, "k": [-0.1, 1.0]}) == -1
+    assert _lib.validate(**{**ok, "mode": [0, 3]}) == -1
+    assert _lib.validate(**{**ok, "windows": [0, 10]}) == -1
+    assert _lib.validate(**{**ok, "elem_size": 4}) == -1
+    assert _lib.validate(**{**ok, "x_ptr": 0}) == -1
+    assert _lib.validate(**{**ok, "lengths": [0, 0], "x_ptr": 0, "y_ptr": 0}) == 0
+    # stats overlapping the output
+    assert _lib.validate(**{**ok, "stats_ptr": ok["y_ptr"]}) == -1
+    assert _lib.validate(**{**ok, "stats_ptr": base + (1 << 18)}) == 0
+    assert _lib.validate(**{**ok, "stats_ptr": base + (1 << 18) + 4}) == -2
+
+
+def test_no_cpu_fallback():
+    """Without a device the filter entry point must fail, not compute."""
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    lib = rfi.load()
+    h = ctypes.c_void_p()
+    L = np.array([4096], np.int64)
+    W = np.array([4096], np.int32)
+    K = np.array([3.0], np.float32)
+    M = np.array([1], np.int32)
+    rc = lib.rfi_plan_create(1, 1, L.ctypes.data, W.ctypes.data, K.ctypes.data, M.ctypes.data, 0,
+                             ctypes.byref(h))
+    assert rc != 0

@@ -1,0 +1,92 @@
+"""int16 parity: radix-select path through the C ABI against the CPU oracle,
+bit-exact in output samples and per-window statistics."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1710_08576_amd as rfi
+from paper_1710_08576_amd import synth
+
+from _helpers import check_against_oracle, gpu_run, unpack
+
+pytestmark = pytest.mark.gpu
+
+MODES = [rfi.ZERO, rfi.CLIP, rfi.NOISE]
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_w8192_tiles_and_tail(gpu, mode):
+    specs = [synth.StreamSpec(8192 * 5 + 3001 + 19 * s, 8192, 3.0, mode, 400.0, 0.01, 32, 32, "i16")
+             for s in range(3)]
+    x = synth.gen_packed(specs, seed=1, tag=20)
+    y, st = gpu_run(x, specs, 8, gpu)
+    check_against_oracle(x, specs, 8, y, st)
+
+
+@pytest.mark.parametrize("W", [1, 2, 5, 100, 1024, 4096, 5000, 16384, 65536])
+@pytest.mark.parametrize("mode", MODES)
+def test_generic_windows(gpu, W, mode):
+    L = max(2 * W + W // 2 + 3, 200)
+    specs = [synth.StreamSpec(L, W, 2.5, mode, 400.0, 0.02, 16, 64, "i16"),
+             synth.StreamSpec(L // 3 + 1, W, 4.0, mode, 30.0, 0.01, 16, 64, "i16")]
+    x = synth.gen_packed(specs, seed=W, tag=21)
+    y, st = gpu_run(x, specs, 6, gpu)
+    check_against_oracle(x, specs, 6, y, st)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_degenerate(gpu, mode):
+    rng = np.random.default_rng(2)
+    W = 8192
+    streams = [np.full(W * 2, -300, np.int16),
+               rng.choice([-32768, 32767], W * 2).astype(np.int16),
+               np.where(rng.random(W * 2) < 0.5, -20000, 20000).astype(np.int16),
+               rng.integers(-32768, 32768, W * 2 + 1).astype(np.int16),
+               np.zeros(0, np.int16),
+               np.array([-32768, 32767], np.int16)]
+    streams[0][17] = 32767
+    x = synth.pack([torch.as_tensor(s) for s in streams])
+    specs = [synth.StreamSpec(len(s), W, 3.0, mode, 1, 0, 1, 1, "i16") for s in streams]
+    y, st = gpu_run(x, specs, 3, gpu)
+    check_against_oracle(x, specs, 3, y, st)
+
+
+def test_all_schedules(gpu):
+    specs = [synth.StreamSpec(8192 * 3 + 100, 8192, 3.0, rfi.NOISE, 400.0, 0.01, 32, 32, "i16"),
+             synth.StreamSpec(9000, 2000, 2.5, rfi.CLIP, 200.0, 0.01, 32, 32, "i16")]
+    x = synth.gen_packed(specs, seed=3, tag=22)
+    ref = None
+    for sched in ("split", "split_persist", "fused", "per_stream"):
+        for graph in (False, True):
+            y, st = gpu_run(x, specs, 1, gpu, schedule=sched, graph=graph, repeat=2)
+            if ref is None:
+                ref = check_against_oracle(x, specs, 1, y, st)
+            else:
+                L, W, _, _ = unpack(specs)
+                so, _, _, _ = rfi.layout(L, W)
+                for o, n in zip(so, L):
+                    assert np.array_equal(y[o:o + n], ref[0][o:o + n]), (sched, graph)
+                assert np.array_equal(st, ref[1])
+
+
+def test_full_size_sampled(gpu):
+    """60 x 2^23 int16, sigma 400, Student-t bursts, W 8192, k 3, noise."""
+    rng = np.random.default_rng(8)
+    specs = synth.int16_path()
+    x = synth.gen_packed(specs, seed=0, tag=30, device=gpu)
+    L, W, K, M = unpack(specs)
+    y, st = rfi.mad_filter(x, L, W, K, M, seed=99)
+    torch.cuda.synchronize()
+    so, wo, nw, _ = rfi.layout(L, W)
+    stn = rfi.stats_numpy(st)
+    picks = rng.integers(0, nw, 80)
+    picks[:2] = [0, nw - 1]
+    for p in picks:
+        s = int(np.searchsorted(wo, p, side="right") - 1)
+        w = int(p - wo[s])
+        a = int(so[s]) + w * 8192
+        xs = x[a:a + 8192].cpu().numpy()
+        yo, sto = oracle.window(xs, K[s], M[s], abs_start=w * 8192, stream=s, seed=99)
+        assert np.array_equal(y[a:a + 8192].cpu().numpy(), yo), (s, w)
+        assert stn[p] == sto, (s, w)

@@ -1,0 +1,162 @@
+"""int8 parity: the HIP path through the C ABI against the CPU oracle,
+bit-exact in output bytes and per-window statistics (Sec. II-D, Eqs. (1)-(2))."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1710_08576_amd as rfi
+from paper_1710_08576_amd import synth
+
+from _helpers import check_against_oracle, gpu_run, unpack
+
+pytestmark = pytest.mark.gpu
+
+MODES = [rfi.ZERO, rfi.CLIP, rfi.NOISE]
+
+
+def _specs(W, mode, n_tiles=3, extra=0, k=3.0, sigma=10.0, frac=0.01, n=2):
+    """Streams spanning several 16 KiB tiles plus a ragged tail."""
+    L = n_tiles * 16384 + extra
+    return [synth.StreamSpec(L + 37 * s, W, k, mode, sigma + 4 * s, frac, 8, 512) for s in range(n)]
+
+
+def test_plain_one_full_size(gpu):
+    """1 stream of 2^20, sigma 10, 0.1 % bursts of 32, W 4096, k 3, clip."""
+    for mode in MODES:
+        specs = synth.plain_one(mode=mode)
+        x = synth.gen_packed(specs, seed=0, tag=0)
+        y, st = gpu_run(x, specs, 0, gpu)
+        check_against_oracle(x, specs, 0, y, st)
+
+
+@pytest.mark.parametrize("W", [512, 1024, 2048, 4096, 8192, 16384])
+@pytest.mark.parametrize("mode", MODES)
+def test_tile_classes(gpu, W, mode):
+    specs = _specs(W, mode, extra=W // 3 + 5)
+    x = synth.gen_packed(specs, seed=W, tag=1)
+    y, st = gpu_run(x, specs, 11, gpu)
+    check_against_oracle(x, specs, 11, y, st)
+
+
+@pytest.mark.parametrize("W", [1, 2, 3, 7, 64, 100, 1000, 4095, 5000, 32768, 65536])
+@pytest.mark.parametrize("mode", MODES)
+def test_generic_windows(gpu, W, mode):
+    L = max(3 * W + W // 2 + 1, 300) if W < 32768 else 2 * W + 999
+    specs = [synth.StreamSpec(L, W, 2.5, mode, 9.0, 0.02, 4, 64),
+             synth.StreamSpec(L // 2 + 3, W, 3.5, mode, 15.0, 0.01, 4, 64)]
+    x = synth.gen_packed(specs, seed=W, tag=2)
+    y, st = gpu_run(x, specs, 5, gpu)
+    check_against_oracle(x, specs, 5, y, st)
+
+
+def _packed_from(streams):
+    return synth.pack([torch.as_tensor(np.asarray(s, dtype=np.int8)) for s in streams])
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_degenerate_windows(gpu, mode):
+    """Constant windows (D = 0), saturated windows, bimodal windows, windows
+    of one and two samples, and a zero-length stream in the batch."""
+    rng = np.random.default_rng(3)
+    W = 4096
+    const = np.full(W * 4, 7, np.int8)
+    const[5] = 8
+    sat = rng.choice([-128, 127], W * 4).astype(np.int8)
+    bimodal = np.where(rng.random(W * 4) < 0.5, -100, 100).astype(np.int8)
+    bimodal += rng.integers(-2, 3, W * 4).astype(np.int8)
+    half = np.concatenate([np.zeros(W * 2, np.int8), np.full(W * 2, 127, np.int8)])
+    streams = [const, sat, bimodal, half, np.zeros(0, np.int8),
+               np.array([-128, 127] * 2049, np.int8), np.array([5] * 4097, np.int8)]
+    x = _packed_from(streams)
+    specs = [synth.StreamSpec(len(s), W, 3.0, mode, 1, 0, 1, 1) for s in streams]
+    y, st = gpu_run(x, specs, 1, gpu)
+    check_against_oracle(x, specs, 1, y, st)
+
+
+@pytest.mark.parametrize("k", [0.0, 0.5, 1.0, 2.0, 3.0, 10.0, 1e4])
+def test_threshold_multiples(gpu, k):
+    specs = [synth.StreamSpec(16384 * 2 + 100, W, k, m, 12.0, 0.01, 8, 64)
+             for W, m in ((4096, rfi.CLIP), (1024, rfi.ZERO), (16384, rfi.NOISE), (1000, rfi.CLIP))]
+    x = synth.gen_packed(specs, seed=int(k * 10), tag=3)
+    y, st = gpu_run(x, specs, 2, gpu)
+    check_against_oracle(x, specs, 2, y, st)
+
+
+def test_mixed_batch_all_schedules_and_graphs(gpu):
+    """Uneven streams with per-stream W, k, mode; every schedule and HIP-graph
+    replay give the same bytes as the oracle."""
+    specs = synth.batching(n_streams=24, lo=1 << 14, hi=1 << 17, seed=4)
+    specs += [synth.StreamSpec(50000, 3000, 3.0, rfi.NOISE, 10.0, 0.01, 8, 64)]
+    x = synth.gen_packed(specs, seed=4, tag=4)
+    ref = None
+    for sched in ("split", "split_persist", "fused", "per_stream"):
+        for graph in (False, True):
+            y, st = gpu_run(x, specs, 9, gpu, schedule=sched, graph=graph, repeat=2)
+            if ref is None:
+                ref = check_against_oracle(x, specs, 9, y, st)
+            else:
+                L, W, _, _ = unpack(specs)
+                so, _, _, _ = rfi.layout(L, W)
+                for o, n in zip(so, L):
+                    assert np.array_equal(y[o:o + n], ref[0][o:o + n]), (sched, graph)
+                assert np.array_equal(st, ref[1]), (sched, graph)
+
+
+def test_in_place(gpu):
+    specs = _specs(4096, rfi.NOISE, extra=1000) + _specs(1000, rfi.ZERO, extra=77)
+    x = synth.gen_packed(specs, seed=5, tag=5)
+    y, st = gpu_run(x, specs, 3, gpu, inplace=True)
+    check_against_oracle(x, specs, 3, y, st, check_padding=False)
+
+
+def test_no_stats_and_determinism(gpu):
+    specs = _specs(2048, rfi.NOISE, extra=999)
+    x = synth.gen_packed(specs, seed=6, tag=6)
+    y1, _ = gpu_run(x, specs, 4, gpu, stats=False)
+    y2, st = gpu_run(x, specs, 4, gpu)
+    assert np.array_equal(y1, y2)
+    check_against_oracle(x, specs, 4, y2, st)
+
+
+def test_argument_errors(gpu):
+    x = torch.zeros(4096 + 64, dtype=torch.int8, device=gpu)
+    y = torch.zeros_like(x)
+    with pytest.raises(rfi.RfiError) as e:
+        rfi.mad_filter(x[1:], [4096], [4096], 3.0, 1, y=y[1:])
+    assert e.value.status == -2
+    for bad in (dict(windows=[0]), dict(windows=[65537]), dict(k=-1.0), dict(k=float("nan")),
+                dict(mode=3), dict(lengths=[-5])):
+        args = dict(lengths=[4096], windows=[4096], k=3.0, mode=1)
+        args.update(bad)
+        with pytest.raises(rfi.RfiError) as e:
+            rfi.mad_filter(x, args["lengths"], args["windows"], args["k"], args["mode"], y=y)
+        assert e.value.status == -1
+    with pytest.raises(rfi.RfiError):  # partial overlap of x and y
+        rfi.mad_filter(x[:4096], [4000], [4096], 3.0, 1, y=x[16:4112])
+
+
+def test_full_size_sampled(gpu):
+    """60 x 2^24 at W 4096 and 16384, in the benchmark's launch
+    configuration; sampled windows are checked one by one against the oracle."""
+    rng = np.random.default_rng(7)
+    for W, mode in ((4096, rfi.CLIP), (4096, rfi.NOISE), (16384, rfi.ZERO)):
+        specs = synth.plain_scale(n_streams=60, length=1 << 24, window=W, mode=mode)
+        x = synth.gen_packed(specs, seed=0, tag=10 + W, device=gpu)
+        L, Wl, K, M = unpack(specs)
+        y, st = rfi.mad_filter(x, L, Wl, K, M, seed=123)
+        torch.cuda.synchronize()
+        so, wo, nw, _ = rfi.layout(L, Wl)
+        picks = rng.integers(0, nw, 120)
+        picks[:2] = [0, nw - 1]
+        stn = rfi.stats_numpy(st)
+        for p in picks:
+            s = int(np.searchsorted(wo, p, side="right") - 1)
+            w = int(p - wo[s])
+            a = int(so[s]) + w * W
+            xs = x[a:a + W].cpu().numpy()
+            yo, sto = oracle.window(xs, K[s], M[s], abs_start=w * W, stream=s, seed=123)
+            assert np.array_equal(y[a:a + W].cpu().numpy(), yo), (W, mode, s, w)
+            assert stn[p] == sto, (W, mode, s, w)
+        del x, y, st
+        torch.cuda.empty_cache()
