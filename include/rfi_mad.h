@@ -132,9 +132,10 @@ typedef enum {
     RFI_SCHED_AUTO = 0,        /* autotuned table, else RFI_SCHED_SPLIT         */
     RFI_SCHED_SPLIT = 1,       /* one launch per window class, one WG per tile  */
     RFI_SCHED_SPLIT_PERSIST = 2, /* one persistent launch per window class     */
-    RFI_SCHED_FUSED = 3,       /* one persistent launch for every class         */
+    RFI_SCHED_FUSED = 3,       /* one launch for every class, one WG per item   */
     RFI_SCHED_PER_STREAM = 4,  /* one ordinary launch per stream (baseline)     */
-    RFI_SCHED_COUNT = 5
+    RFI_SCHED_FUSED_PERSIST = 5, /* one persistent launch for every class      */
+    RFI_SCHED_COUNT = 6
 } rfi_schedule;
 
 /* elem_size 1 or 2; arrays as in rfi_mad_filter.  Allocates device work

@@ -1,0 +1,32 @@
+/*
+ * rfi_ubench.h -- microbenchmark kernels shipped with librfimad.
+ *
+ * rfi_ubench_copy: a plain device-to-device copy used to measure the HBM
+ * streaming ceiling of the GPU (the denominator next to the 8 TB/s peak) and
+ * to calibrate the FETCH_SIZE / WRITE_SIZE hardware counters against a
+ * kernel whose traffic is known (one read and one write per byte).
+ *   x, y     device pointers, 16-byte aligned, non-overlapping.
+ *   bytes    multiple of 16384.
+ *   variant  0: 64 bytes per lane as four 16-byte loads (the tile shape of
+ *               the filter kernels), one workgroup per 16 KiB;
+ *            1: as 0 with non-temporal loads and stores;
+ *            2: 16 bytes per lane, grid-stride loop over a persistent grid.
+ *   stream   hipStream_t (NULL = null stream).
+ * Returns 0, RFI_ERR_INVALID (-1) or RFI_ERR_ALIGN (-2); asynchronous.
+ */
+#ifndef RFI_UBENCH_H
+#define RFI_UBENCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+int rfi_ubench_copy(const void* x, void* y, uint64_t bytes, int32_t variant, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

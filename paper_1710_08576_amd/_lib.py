@@ -15,13 +15,15 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librfimad.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "rfi_mad.h")
+HEADERS = [HEADER, os.path.join(os.path.dirname(_HERE), "include", "rfi_ubench.h")]
 
 RFI_OK = 0
 STATUS = {0: "RFI_OK", -1: "RFI_ERR_INVALID", -2: "RFI_ERR_ALIGN", -3: "RFI_ERR_UNSUPPORTED",
           -4: "RFI_ERR_NOMEM", -5: "RFI_ERR_HIP", -6: "RFI_ERR_BUSY"}
 ZERO, CLIP, NOISE = 0, 1, 2
-SCHED_AUTO, SCHED_SPLIT, SCHED_SPLIT_PERSIST, SCHED_FUSED, SCHED_PER_STREAM = range(5)
-SCHEDULES = {"auto": 0, "split": 1, "split_persist": 2, "fused": 3, "per_stream": 4}
+SCHED_AUTO, SCHED_SPLIT, SCHED_SPLIT_PERSIST, SCHED_FUSED, SCHED_PER_STREAM, SCHED_FUSED_PERSIST = range(6)
+SCHEDULES = {"auto": 0, "split": 1, "split_persist": 2, "fused": 3, "per_stream": 4,
+             "fused_persist": 5}
 
 STATS_DTYPE = np.dtype(
     [("median", "<i4"), ("mad", "<i4"), ("n_flagged", "<u4"), ("threshold", "<f4")]
@@ -73,13 +75,17 @@ _SIGS = {
     "rfi_server_restore": (ctypes.c_int, [P, U32, I64, I32, P]),
     "rfi_server_counters": (ctypes.c_int, [P, P, P, P, P]),
     "rfi_server_destroy": (ctypes.c_int, [P]),
+    "rfi_ubench_copy": (ctypes.c_int, [P, P, U64, I32, P]),
 }
 
 
 def header_symbols() -> list[str]:
-    """Every function the public header declares."""
-    text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(rfi_\w+)\s*\(", text, re.M)))
+    """Every function the public headers declare."""
+    names = set()
+    for h in HEADERS:
+        text = open(h).read()
+        names |= set(re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(rfi_\w+)\s*\(", text, re.M))
+    return sorted(names)
 
 
 def load():
@@ -142,6 +148,13 @@ def validate(elem_size, x_ptr, y_ptr, lengths, windows, k, mode, stats_ptr=0) ->
     W, K, M = _arr(windows, np.int32, n), _arr(k, np.float32, n), _arr(mode, np.int32, n)
     return load().rfi_validate(elem_size, P(x_ptr), P(y_ptr), n, _ptr(L), _ptr(W), _ptr(K),
                                _ptr(M), P(stats_ptr))
+
+
+def ubench_copy(x, y, variant=0, stream=None):
+    """HBM copy microbenchmark kernel: y[:] = x[:] (bytes a multiple of 16 KiB)."""
+    nbytes = x.numel() * x.element_size()
+    _check(load().rfi_ubench_copy(_tptr(x), _tptr(y), nbytes, variant, _stream_handle(stream)),
+           "rfi_ubench_copy")
 
 
 def stats_numpy(stats_t) -> np.ndarray:

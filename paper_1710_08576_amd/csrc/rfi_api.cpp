@@ -73,7 +73,7 @@ void record_schedule(uint64_t sig, int sched)
 struct PlanLaunch {
     int kind;   // 0 tiles of one class, 1 generic, 2 fused
     int cls;    // tile class for kind 0
-    bool noise; // tile kernel with the noise path
+    int modes;  // bit m: some stream of the launch uses mode m
     int64_t first, count;
     int grid;
 };
@@ -130,7 +130,7 @@ static hipError_t run_launch(const rfi_plan* p, const PlanLaunch& l, const Launc
     a.items = p->ditems + l.first;
     a.n_items = l.count;
     if (p->elem == 1) {
-        if (l.kind == 0) return launch_i8_tiles(l.cls, l.noise, a, l.grid, s);
+        if (l.kind == 0) return launch_i8_tiles(l.cls, l.modes, a, l.grid, s);
         if (l.kind == 1) return launch_i8_generic(a, l.grid, s);
         return launch_i8_fused(a, l.grid, s);
     }
@@ -146,7 +146,7 @@ static void build_launches(rfi_plan* p)
     // Items are ordered: generic items, then tiles of class 0, 1, ...; in
     // each group by stream, then position.  Ranges per group:
     std::vector<int64_t> gbegin(ncls + 1, 0), gend(ncls + 1, 0);
-    std::vector<bool> gnoise(ncls + 1, false);
+    std::vector<int> gmodes(ncls + 1, 0);
     {
         int64_t pos = 0;
         for (int g = 0; g <= ncls; ++g) {
@@ -156,7 +156,7 @@ static void build_launches(rfi_plan* p)
                 const int cls = it.kind == kItemGeneric ? -1 : tile_class(elem, p->W[it.stream]);
                 const int grp = cls < 0 ? 0 : cls + 1;
                 if (grp != g) break;
-                if (p->M[it.stream] == RFI_MODE_NOISE) gnoise[g] = true;
+                gmodes[g] |= 1 << p->M[it.stream];
                 ++pos;
             }
             gend[g] = pos;
@@ -169,15 +169,16 @@ static void build_launches(rfi_plan* p)
         const int64_t c = gend[g] - gbegin[g];
         if (c == 0) continue;
         const int cls = g - 1;
-        PlanLaunch l{g == 0 ? 1 : 0, cls, (bool)gnoise[g], gbegin[g], c, clamp_grid(c)};
+        PlanLaunch l{g == 0 ? 1 : 0, cls, gmodes[g], gbegin[g], c, clamp_grid(c)};
         p->launches[RFI_SCHED_SPLIT].push_back(l);
-        l.grid = (int)std::min<int64_t>(c, persistent_grid(elem, cls, l.noise, false));
+        l.grid = (int)std::min<int64_t>(c, persistent_grid(elem, cls, l.modes, false));
         p->launches[RFI_SCHED_SPLIT_PERSIST].push_back(l);
     }
     if (n_items > 0) {
-        PlanLaunch f{2, -1, true, 0, n_items,
-                     (int)std::min<int64_t>(n_items, persistent_grid(elem, -1, true, true))};
+        PlanLaunch f{2, -1, 7, 0, n_items, clamp_grid(n_items)};
         p->launches[RFI_SCHED_FUSED].push_back(f);
+        f.grid = (int)std::min<int64_t>(n_items, persistent_grid(elem, -1, 7, true));
+        p->launches[RFI_SCHED_FUSED_PERSIST].push_back(f);
     }
     // One ordinary launch per stream and kind (the plain baseline).
     for (int s = 0; s < p->n; ++s) {
@@ -192,7 +193,7 @@ static void build_launches(rfi_plan* p)
                 }
             }
             if (b < 0) continue;
-            PlanLaunch l{g == 0 ? 1 : 0, g - 1, p->M[s] == RFI_MODE_NOISE, b, e - b, clamp_grid(e - b)};
+            PlanLaunch l{g == 0 ? 1 : 0, g - 1, 1 << p->M[s], b, e - b, clamp_grid(e - b)};
             p->launches[RFI_SCHED_PER_STREAM].push_back(l);
         }
     }
@@ -477,7 +478,8 @@ int rfi_plan_autotune(rfi_plan* plan, const void* x, void* y, rfi_window_stats* 
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return hip_fail(hipGetLastError());
     int best = RFI_SCHED_SPLIT;
     float best_t = 1e30f;
-    const int cands[] = {RFI_SCHED_SPLIT, RFI_SCHED_SPLIT_PERSIST, RFI_SCHED_FUSED};
+    const int cands[] = {RFI_SCHED_SPLIT, RFI_SCHED_SPLIT_PERSIST, RFI_SCHED_FUSED,
+                         RFI_SCHED_FUSED_PERSIST};
     for (int c : cands) {
         if (plan->launches[c].empty()) continue;
         rc = plan_execute(plan, x, y, stats_out, s, c);  // warm-up (graph capture)

@@ -22,17 +22,49 @@ __device__ __forceinline__ void wave_sync()
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
-// Inclusive prefix sum within aligned groups of G lanes (G a power of two).
+// DPP lane move with zero fill: lanes whose source is outside the row (or
+// whose row is masked off) receive 0.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ uint32_t dpp0(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, false);
+}
+
+// Inclusive prefix sum within aligned groups of G lanes (G a power of two,
+// G <= 64), on DPP row shifts and row broadcasts (no LDS round trip).
 template <int G>
 __device__ __forceinline__ uint32_t group_incl_scan(uint32_t v)
 {
-    const int l = lane_id() & (G - 1);
-#pragma unroll
-    for (int d = 1; d < G; d <<= 1) {
-        const uint32_t t = __shfl_up(v, d, G);
-        if (l >= d) v += t;
+    if constexpr (G >= 2) {
+        const int l = lane_id() & 15;
+        uint32_t t = dpp0<0x111>(v);  // row_shr:1
+        v += (G >= 16 || (l & (G - 1)) >= 1) ? t : 0u;
+        if constexpr (G >= 4) {
+            t = dpp0<0x112>(v);  // row_shr:2
+            v += (G >= 16 || (l & (G - 1)) >= 2) ? t : 0u;
+        }
+        if constexpr (G >= 8) {
+            t = dpp0<0x114>(v);  // row_shr:4
+            v += (G >= 16 || (l & (G - 1)) >= 4) ? t : 0u;
+        }
+        if constexpr (G >= 16) v += dpp0<0x118>(v);        // row_shr:8
+        if constexpr (G >= 32) v += dpp0<0x142, 0xA>(v);   // row_bcast:15 into rows 1, 3
+        if constexpr (G >= 64) v += dpp0<0x143, 0xC>(v);   // row_bcast:31 into rows 2, 3
     }
     return v;
+}
+
+// Number of lanes of this lane's aligned group of G whose predicate holds.
+template <int G>
+__device__ __forceinline__ int group_count(bool pred)
+{
+    const uint64_t b = __ballot(pred);
+    if constexpr (G == 64) {
+        return (int)__popcll(b);
+    } else {
+        const int shift = lane_id() & ~(G - 1);
+        return (int)__popc((uint32_t)(b >> shift) & (uint32_t)((1ull << G) - 1));
+    }
 }
 
 template <int G>
@@ -52,6 +84,61 @@ __device__ __forceinline__ uint32_t group_sum(uint32_t v)
 }
 
 // ------------------------------------------------------------------------
+// Global-memory access.  Stream addresses are rebuilt from integer offsets,
+// so the compiler cannot see that they point to global memory; these casts
+// keep the sample traffic on global_load/global_store instead of flat.
+// ------------------------------------------------------------------------
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const u32x4 g_cu32x4;
+typedef __attribute__((address_space(1))) u32x4 g_u32x4;
+
+__device__ __forceinline__ uint4 gload16(const void* p)
+{
+    const u32x4 t = *(g_cu32x4*)p;
+    return make_uint4(t.x, t.y, t.z, t.w);
+}
+__device__ __forceinline__ void gstore16(void* p, uint4 v)
+{
+    u32x4 t;
+    t.x = v.x;
+    t.y = v.y;
+    t.z = v.z;
+    t.w = v.w;
+    *(g_u32x4*)p = t;
+}
+
+// Non-temporal variants for the sample stream (read once, written once).
+__device__ __forceinline__ uint4 gload16_nt(const void* p)
+{
+    const u32x4 t = __builtin_nontemporal_load((g_cu32x4*)p);
+    return make_uint4(t.x, t.y, t.z, t.w);
+}
+__device__ __forceinline__ void gstore16_nt(void* p, uint4 v)
+{
+    u32x4 t;
+    t.x = v.x;
+    t.y = v.y;
+    t.z = v.z;
+    t.w = v.w;
+    __builtin_nontemporal_store(t, (g_u32x4*)p);
+}
+
+template <typename T>
+__device__ __forceinline__ T gload(const T* p)
+{
+    return *(__attribute__((address_space(1))) const T*)p;
+}
+template <typename T>
+__device__ __forceinline__ void gstore(T* p, T v)
+{
+    *(__attribute__((address_space(1))) T*)p = v;
+}
+
+// Keeps the scheduler from hoisting work across this point (limits the
+// number of live registers in long unrolled sequences).
+__device__ __forceinline__ void sched_fence() { __builtin_amdgcn_sched_barrier(0); }
+
+// ------------------------------------------------------------------------
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
 // 64x64->128 multiplies; the key is bumped by the two Weyl constants after
 // every round.
@@ -59,6 +146,19 @@ __device__ __forceinline__ uint32_t group_sum(uint32_t v)
 struct Philox4x64 {
     uint64_t w[4];
 };
+
+// Full 64 x 64 -> 128-bit product from four 32 x 32 -> 64 partial products,
+// each a single v_mad_u64_u32 with the carry-in folded into the addend.
+__device__ __forceinline__ void mul64_wide(uint64_t a, uint64_t k, uint64_t& lo, uint64_t& hi)
+{
+    const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+    const uint32_t k0 = (uint32_t)k, k1 = (uint32_t)(k >> 32);
+    const uint64_t p00 = (uint64_t)a0 * k0;
+    const uint64_t t = (uint64_t)a0 * k1 + (p00 >> 32);
+    const uint64_t u = (uint64_t)a1 * k0 + (uint32_t)t;
+    lo = (uint64_t)(uint32_t)p00 | (u << 32);
+    hi = (uint64_t)a1 * k1 + (t >> 32) + (u >> 32);
+}
 
 __device__ __forceinline__ Philox4x64 philox4x64_10(uint64_t ctr0, uint64_t key0, uint64_t key1)
 {
@@ -69,8 +169,9 @@ __device__ __forceinline__ Philox4x64 philox4x64_10(uint64_t ctr0, uint64_t key0
     uint64_t a = ctr0, b = 0, c = 0, d = 0;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint64_t pa_lo = a * kMulA, pa_hi = __umul64hi(a, kMulA);
-        const uint64_t pc_lo = c * kMulB, pc_hi = __umul64hi(c, kMulB);
+        uint64_t pa_lo, pa_hi, pc_lo, pc_hi;
+        mul64_wide(a, kMulA, pa_lo, pa_hi);
+        mul64_wide(c, kMulB, pc_lo, pc_hi);
         const uint64_t na = pc_hi ^ b ^ key0;
         const uint64_t nc = pa_hi ^ d ^ key1;
         a = na;

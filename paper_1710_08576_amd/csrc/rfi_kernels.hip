@@ -82,12 +82,15 @@ __device__ __forceinline__ void select_i8(uint32_t* hw, uint32_t need, int& mb, 
 #pragma unroll
     for (int j = 0; j < BPL; j += 4)
         *reinterpret_cast<uint4*>(my + j) = make_uint4(c[j], c[j + 1], c[j + 2], c[j + 3]);
+    // C is non-decreasing in the bin, and bins run in lane order, so the
+    // median bin is the number of bins with C < need.
     int below = 0;
 #pragma unroll
-    for (int j = 0; j < BPL; ++j) below += (c[j] < need) ? 1 : 0;
-    mb = group_min<G>(below < BPL ? sl * BPL + below : 256);
+    for (int j = 0; j < BPL; ++j) below += group_count<G>(c[j] < need);
+    mb = below;
     wave_sync();
-    // #{|x - m| <= d} = C[min(mb + d, 255)] - C[mb - d - 1] is non-decreasing in d.
+    // #{|x - m| <= d} = C[min(mb + d, 255)] - C[mb - d - 1] is non-decreasing
+    // in d, so D is the number of d with a count below `need`.
     int dbelow = 0;
 #pragma unroll
     for (int j = 0; j < BPL; ++j) {
@@ -95,9 +98,9 @@ __device__ __forceinline__ void select_i8(uint32_t* hw, uint32_t need, int& mb, 
         const int up = min(mb + d, 255);
         const int dn = mb - d - 1;
         const uint32_t lowc = dn >= 0 ? hw[max(dn, 0)] : 0u;
-        dbelow += (hw[up] - lowc < need) ? 1 : 0;
+        dbelow += group_count<G>(hw[up] - lowc < need);
     }
-    D = group_min<G>(dbelow < BPL ? sl * BPL + dbelow : 256);
+    D = dbelow;
 }
 
 // Window parameters and statistics from the cumulative histogram hw.
@@ -139,27 +142,35 @@ __device__ __forceinline__ void merge_noise(uint32_t (&v)[16], uint32_t fl, uint
     const uint32_t cnt = __popc(fl);
     const uint32_t incl = group_incl_scan<64>(cnt);
     const int base = (int)(incl - cnt);
-    const int F = (int)__shfl(incl, 63);
+    const int F = __builtin_amdgcn_readlane((int)incl, 63);
     for (int r0 = 0; r0 < F; r0 += 256) {
+        int e = base - r0;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-            const int e = base + __popc(fl & ((1u << q) - 1u)) - r0;
-            if (((fl >> q) & 1u) && e >= 0 && e < 256) list[e] = (uint32_t)(lane << 4 | q);
+            if ((fl >> q) & 1u) {
+                if (e >= 0 && e < 256) list[e] = (uint32_t)(lane << 4 | q);
+                ++e;
+            }
+            sched_fence();
         }
         wave_sync();
         const int nE = min(256, F - r0);
-        for (int e = lane; e < nE; e += 64) {
-            const uint32_t ent = list[e];
-            stage[e] = dword_noise((int)(ent >> 4), (int)(ent & 15u));
+        for (int i = lane; i < nE; i += 64) {
+            const uint32_t ent = list[i];
+            stage[i] = dword_noise((int)(ent >> 4), (int)(ent & 15u));
         }
         wave_sync();
+        e = base - r0;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-            const int e = base + __popc(fl & ((1u << q) - 1u)) - r0;
-            if (((fl >> q) & 1u) && e >= 0 && e < 256) {
-                const uint32_t mk = mask_of(q);
-                v[q] = (v[q] & ~mk) | (stage[e] & mk);
+            if ((fl >> q) & 1u) {
+                if (e >= 0 && e < 256) {
+                    const uint32_t mk = mask_of(q);
+                    v[q] = (v[q] & ~mk) | (stage[e] & mk);
+                }
+                ++e;
             }
+            sched_fence();
         }
         wave_sync();
     }
@@ -176,10 +187,11 @@ struct I8TileSmem {
     uint32_t noise[NOISE ? 4 * 512 : 1];
 };
 
-template <int W, bool NOISE>
+template <int W, bool NOISE, int MODE>
 __device__ __forceinline__ void i8_tile(const StreamView& d, int64_t first, uint64_t seed,
                                         I8TileSmem<W, NOISE>& sm)
 {
+    static_assert(MODE != RFI_MODE_NOISE || NOISE, "noise needs its LDS scratch");
     constexpr int NWW = W < 4096 ? 4096 / W : 1;  // windows per wave
     constexpr int WPW = W > 4096 ? W / 4096 : 1;  // waves per window
     constexpr int G = 64 / NWW;                   // lanes per window in the scan
@@ -192,7 +204,7 @@ __device__ __forceinline__ void i8_tile(const StreamView& d, int64_t first, uint
     uint32_t v[16];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const uint4 t = *reinterpret_cast<const uint4*>(xt + i * 1024);
+        const uint4 t = gload16_nt(xt + i * 1024);
         v[4 * i] = t.x;
         v[4 * i + 1] = t.y;
         v[4 * i + 2] = t.z;
@@ -223,6 +235,7 @@ __device__ __forceinline__ void i8_tile(const StreamView& d, int64_t first, uint
             atomicAdd(&h[(u >> 8) & 0xFFu], 1u);
             atomicAdd(&h[(u >> 16) & 0xFFu], 1u);
             atomicAdd(&h[u >> 24], 1u);
+            sched_fence();
         }
     }
 
@@ -260,16 +273,18 @@ __device__ __forceinline__ void i8_tile(const StreamView& d, int64_t first, uint
     }
 
     // Replacement (Eq. (2)).
-    const int mode = d.mode;
-    if (mode == RFI_MODE_CLIP) {
+    if constexpr (MODE == RFI_MODE_CLIP) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const WinParams p = sm.prm[(wbase + i * 1024 + lane * 16) / W];
             const uint32_t lo = rep_i16(p.lo * 256), hi = rep_i16(p.hi * 256);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) v[4 * i + j] = clamp_i8x4(v[4 * i + j], lo, hi);
+            for (int j = 0; j < 4; ++j) {
+                v[4 * i + j] = clamp_i8x4(v[4 * i + j], lo, hi);
+                sched_fence();
+            }
         }
-    } else if (!NOISE || mode == RFI_MODE_ZERO) {
+    } else if constexpr (MODE == RFI_MODE_ZERO) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const WinParams p = sm.prm[(wbase + i * 1024 + lane * 16) / W];
@@ -278,9 +293,10 @@ __device__ __forceinline__ void i8_tile(const StreamView& d, int64_t first, uint
             for (int j = 0; j < 4; ++j) {
                 const uint32_t x = v[4 * i + j];
                 v[4 * i + j] = x & ~nonzero_byte_mask(clamp_i8x4(x, lo, hi) ^ x);
+                sched_fence();
             }
         }
-    } else if constexpr (NOISE) {
+    } else {
         uint32_t fl = 0;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -290,6 +306,7 @@ __device__ __forceinline__ void i8_tile(const StreamView& d, int64_t first, uint
             for (int j = 0; j < 4; ++j) {
                 const uint32_t x = v[4 * i + j];
                 fl |= (clamp_i8x4(x, lo, hi) != x ? 1u : 0u) << (4 * i + j);
+                sched_fence();
             }
         }
         const int64_t abs0 = d.abs_base + first + wbase;
@@ -319,8 +336,26 @@ __device__ __forceinline__ void i8_tile(const StreamView& d, int64_t first, uint
 
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-        *reinterpret_cast<uint4*>(yt + i * 1024) =
-            make_uint4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]);
+        gstore16_nt(yt + i * 1024, make_uint4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]));
+}
+
+// Mode dispatch: MODES is the set (bit m = mode m) compiled into a kernel.
+template <int W, bool NOISE, int MODES>
+__device__ __forceinline__ void i8_tile_any(const StreamView& d, int64_t first, uint64_t seed,
+                                            I8TileSmem<W, NOISE>& sm)
+{
+    static_assert(!(MODES & 4) || NOISE, "noise needs its LDS scratch");
+    if constexpr (MODES == 1) {
+        i8_tile<W, NOISE, RFI_MODE_ZERO>(d, first, seed, sm);
+    } else if constexpr (MODES == 2) {
+        i8_tile<W, NOISE, RFI_MODE_CLIP>(d, first, seed, sm);
+    } else if constexpr (MODES == 4) {
+        i8_tile<W, NOISE, RFI_MODE_NOISE>(d, first, seed, sm);
+    } else {
+        if ((MODES & 2) && d.mode == RFI_MODE_CLIP) i8_tile<W, NOISE, RFI_MODE_CLIP>(d, first, seed, sm);
+        else if ((MODES & 1) && d.mode == RFI_MODE_ZERO) i8_tile<W, NOISE, RFI_MODE_ZERO>(d, first, seed, sm);
+        else if constexpr ((MODES & 4) != 0) i8_tile<W, NOISE, RFI_MODE_NOISE>(d, first, seed, sm);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -337,8 +372,8 @@ struct GenericSmem {
 template <typename T>
 __device__ __forceinline__ int load_logical(const StreamView& d, int64_t i)
 {
-    return i < d.head_len ? (int)static_cast<const T*>(d.x_head)[i]
-                          : (int)static_cast<const T*>(d.x)[i - d.head_len];
+    return i < d.head_len ? (int)gload(static_cast<const T*>(d.x_head) + i)
+                          : (int)gload(static_cast<const T*>(d.x) + (i - d.head_len));
 }
 
 __device__ __forceinline__ int noise_sample(int64_t j, uint64_t seed, uint32_t key, int m, int sq8,
@@ -383,7 +418,7 @@ __device__ void i8_generic(const StreamView& d, int64_t w, uint64_t seed, Generi
             else if (d.mode == RFI_MODE_CLIP) yv = min(max(x, p.lo), p.hi);
             else yv = noise_sample(d.abs_base + a + i, seed, d.key, p.m, p.sq8, -128, 127);
         }
-        y[a + i] = (int8_t)yv;
+        gstore(y + a + i, (int8_t)yv);
     }
 }
 
@@ -419,20 +454,19 @@ __device__ __forceinline__ void bucket_of(const uint32_t* hw, uint32_t need, int
     for (int j = 1; j < 4; ++j) c[j] += c[j - 1];
     const uint32_t incl = group_incl_scan<64>(c[3]);
     const uint32_t excl = incl - c[3];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) c[j] += excl;
+    // Bins run in lane order and C is non-decreasing: the bucket holding
+    // rank `need` is the number of bins with C < need.
     int nb = 0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) nb += (c[j] + excl < need) ? 1 : 0;
-    // lane holding the bucket: first lane with nb < 4
-    const int cand = nb < 4 ? lane * 4 + nb : 255;
-    bucket = group_min<64>(cand);  // 255 if the histogram held fewer than `need`
-    // count below the bucket: cumulative count of bucket - 1
-    const int src_lane = (bucket - 1) >> 2, src_j = (bucket - 1) & 3;
-    uint32_t mine = 0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-        if (j == src_j) mine = c[j] + excl;
-    const uint32_t got = __shfl(mine, max(src_lane, 0));
-    below = bucket > 0 ? got : 0u;
+    for (int j = 0; j < 4; ++j) nb += group_count<64>(c[j] < need);
+    bucket = min(nb, 255);  // 255 only if the histogram held fewer than `need`
+    const int prev = bucket - 1;
+    const int pj = prev & 3;
+    const uint32_t mine = pj == 0 ? c[0] : pj == 1 ? c[1] : pj == 2 ? c[2] : c[3];
+    const uint32_t got = (uint32_t)__builtin_amdgcn_readlane((int)mine, max(prev, 0) >> 2);
+    below = prev >= 0 ? got : 0u;
 }
 
 __device__ __forceinline__ void zero_words(uint32_t* p, int words, int tid, int nthreads)
@@ -469,7 +503,7 @@ __device__ void i16_tile_8192(const StreamView& d, int64_t first, uint64_t seed,
     uint32_t v[16];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const uint4 t = *reinterpret_cast<const uint4*>(xt + i * 1024);
+        const uint4 t = gload16_nt(xt + i * 1024);
         v[4 * i] = t.x;
         v[4 * i + 1] = t.y;
         v[4 * i + 2] = t.z;
@@ -490,6 +524,7 @@ __device__ void i16_tile_8192(const StreamView& d, int64_t first, uint64_t seed,
         const uint32_t u = v[q] ^ 0x80008000u;
         atomicAdd(&sm.h1[((u >> 8) & 0xFFu) * R + rep], 1u);
         atomicAdd(&sm.h1[(u >> 24) * R + rep], 1u);
+        sched_fence();
     }
     __syncthreads();
     constexpr uint32_t need = (W - 1) / 2 + 1;
@@ -514,6 +549,7 @@ __device__ void i16_tile_8192(const StreamView& d, int64_t first, uint64_t seed,
         const uint32_t d0 = (uint32_t)abs(lo16(v[q]) - m), d1 = (uint32_t)abs(hi16(v[q]) - m);
         atomicAdd(&sm.h3[(d0 >> 8) * R + rep], 1u);
         atomicAdd(&sm.h3[(d1 >> 8) * R + rep], 1u);
+        sched_fence();
     }
     __syncthreads();
     int b3;
@@ -574,8 +610,7 @@ __device__ void i16_tile_8192(const StreamView& d, int64_t first, uint64_t seed,
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-        *reinterpret_cast<uint4*>(yt + i * 1024) =
-            make_uint4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]);
+        gstore16_nt(yt + i * 1024, make_uint4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]));
     nflag = group_sum<64>(nflag);
     if (lane == 0) atomicAdd(&sm.flagged, nflag);
     __syncthreads();
@@ -676,7 +711,7 @@ __device__ void i16_generic(const StreamView& d, int64_t w, uint64_t seed, Gener
             else if (d.mode == RFI_MODE_CLIP) yv = min(max(x, lo), hi);
             else yv = noise_sample(d.abs_base + a + i, seed, d.key, m, sq8, -32768, 32767);
         }
-        y[a + i] = (int16_t)yv;
+        gstore(y + a + i, (int16_t)yv);
     }
     nflag = group_sum<64>(nflag);
     if (lane_id() == 0) atomicAdd(&sm.flagged, nflag);
@@ -695,26 +730,41 @@ __device__ void i16_generic(const StreamView& d, int64_t w, uint64_t seed, Gener
 // Kernels.  All loop over items with a grid stride, so the same kernel
 // serves one-workgroup-per-item launches and persistent launches.
 // ---------------------------------------------------------------------------
-template <int CLS, bool NOISE>
-__global__ __launch_bounds__(kBlock) void k_i8_tiles(LaunchArgs a)
+// Runs body(item_index) for this workgroup's items.  PERSIST: grid-stride
+// loop; otherwise exactly one item per workgroup (no loop, so nothing is
+// kept live across items).
+template <bool PERSIST, class Body>
+__device__ __forceinline__ void for_items(const LaunchArgs& a, Body body)
 {
-    constexpr int W = 512 << CLS;
-    __shared__ I8TileSmem<W, NOISE> sm;
-    for (int64_t it = blockIdx.x; it < a.n_items; it += gridDim.x) {
-        const Item item = a.items[it];
-        const StreamView d = resolve(a.streams[item.stream], a);
-        i8_tile<W, NOISE>(d, item.first, a.seed, sm);
+    if constexpr (PERSIST) {
+        for (int64_t it = blockIdx.x; it < a.n_items; it += gridDim.x) body(it);
+    } else {
+        if ((int64_t)blockIdx.x < a.n_items) body((int64_t)blockIdx.x);
     }
 }
 
+template <int CLS, int MODES, bool PERSIST>
+__global__ __launch_bounds__(kBlock) void k_i8_tiles(LaunchArgs a)
+{
+    constexpr int W = 512 << CLS;
+    constexpr bool NOISE = (MODES & 4) != 0;
+    __shared__ I8TileSmem<W, NOISE> sm;
+    for_items<PERSIST>(a, [&](int64_t it) {
+        const Item item = a.items[it];
+        const StreamView d = resolve(a.streams[item.stream], a);
+        i8_tile_any<W, NOISE, MODES>(d, item.first, a.seed, sm);
+    });
+}
+
+template <bool PERSIST>
 __global__ __launch_bounds__(kBlock) void k_i8_generic(LaunchArgs a)
 {
     __shared__ GenericSmem sm;
-    for (int64_t it = blockIdx.x; it < a.n_items; it += gridDim.x) {
+    for_items<PERSIST>(a, [&](int64_t it) {
         const Item item = a.items[it];
         const StreamView d = resolve(a.streams[item.stream], a);
         i8_generic(d, item.first, a.seed, sm);
-    }
+    });
 }
 
 union I8FusedSmem {
@@ -727,48 +777,51 @@ union I8FusedSmem {
     GenericSmem g;
 };
 
+template <bool PERSIST>
 __global__ __launch_bounds__(kBlock) void k_i8_fused(LaunchArgs a)
 {
     __shared__ I8FusedSmem sm;
-    for (int64_t it = blockIdx.x; it < a.n_items; it += gridDim.x) {
+    for_items<PERSIST>(a, [&](int64_t it) {
         const Item item = a.items[it];
         const StreamView d = resolve(a.streams[item.stream], a);
         if (item.kind == kItemGeneric) {
             i8_generic(d, item.first, a.seed, sm.g);
-            continue;
+            return;
         }
         // Items of different classes may follow each other: keep the LDS
         // of the previous item alive until every wave is done with it.
         __syncthreads();
         switch (i8_tile_class(d.window)) {
-            case 0: i8_tile<512, true>(d, item.first, a.seed, sm.c0); break;
-            case 1: i8_tile<1024, true>(d, item.first, a.seed, sm.c1); break;
-            case 2: i8_tile<2048, true>(d, item.first, a.seed, sm.c2); break;
-            case 3: i8_tile<4096, true>(d, item.first, a.seed, sm.c3); break;
-            case 4: i8_tile<8192, true>(d, item.first, a.seed, sm.c4); break;
-            default: i8_tile<16384, true>(d, item.first, a.seed, sm.c5); break;
+            case 0: i8_tile_any<512, true, 7>(d, item.first, a.seed, sm.c0); break;
+            case 1: i8_tile_any<1024, true, 7>(d, item.first, a.seed, sm.c1); break;
+            case 2: i8_tile_any<2048, true, 7>(d, item.first, a.seed, sm.c2); break;
+            case 3: i8_tile_any<4096, true, 7>(d, item.first, a.seed, sm.c3); break;
+            case 4: i8_tile_any<8192, true, 7>(d, item.first, a.seed, sm.c4); break;
+            default: i8_tile_any<16384, true, 7>(d, item.first, a.seed, sm.c5); break;
         }
-    }
+    });
 }
 
+template <bool PERSIST>
 __global__ __launch_bounds__(kBlock) void k_i16_tiles(LaunchArgs a)
 {
     __shared__ I16TileSmem sm;
-    for (int64_t it = blockIdx.x; it < a.n_items; it += gridDim.x) {
+    for_items<PERSIST>(a, [&](int64_t it) {
         const Item item = a.items[it];
         const StreamView d = resolve(a.streams[item.stream], a);
         i16_tile_8192(d, item.first, a.seed, sm);
-    }
+    });
 }
 
+template <bool PERSIST>
 __global__ __launch_bounds__(kBlock) void k_i16_generic(LaunchArgs a)
 {
     __shared__ GenericSmem sm;
-    for (int64_t it = blockIdx.x; it < a.n_items; it += gridDim.x) {
+    for_items<PERSIST>(a, [&](int64_t it) {
         const Item item = a.items[it];
         const StreamView d = resolve(a.streams[item.stream], a);
         i16_generic(d, item.first, a.seed, sm);
-    }
+    });
 }
 
 union I16FusedSmem {
@@ -776,15 +829,16 @@ union I16FusedSmem {
     GenericSmem g;
 };
 
+template <bool PERSIST>
 __global__ __launch_bounds__(kBlock) void k_i16_fused(LaunchArgs a)
 {
     __shared__ I16FusedSmem sm;
-    for (int64_t it = blockIdx.x; it < a.n_items; it += gridDim.x) {
+    for_items<PERSIST>(a, [&](int64_t it) {
         const Item item = a.items[it];
         const StreamView d = resolve(a.streams[item.stream], a);
         if (item.kind == kItemGeneric) i16_generic(d, item.first, a.seed, sm.g);
         else i16_tile_8192(d, item.first, a.seed, sm.t);
-    }
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -799,47 +853,80 @@ static hipError_t launch(void (*k)(LaunchArgs), const LaunchArgs& a, int grid, h
     return hipLaunchKernel(reinterpret_cast<const void*>(k), dim3(grid), dim3(kBlock), kargs, 0, s);
 }
 
-template <bool NOISE>
-static void (*i8_tile_kernel(int cls))(LaunchArgs)
+template <int MODES, bool PERSIST>
+static void (*i8_tile_kernel_m(int cls))(LaunchArgs)
 {
     switch (cls) {
-        case 0: return k_i8_tiles<0, NOISE>;
-        case 1: return k_i8_tiles<1, NOISE>;
-        case 2: return k_i8_tiles<2, NOISE>;
-        case 3: return k_i8_tiles<3, NOISE>;
-        case 4: return k_i8_tiles<4, NOISE>;
-        case 5: return k_i8_tiles<5, NOISE>;
+        case 0: return k_i8_tiles<0, MODES, PERSIST>;
+        case 1: return k_i8_tiles<1, MODES, PERSIST>;
+        case 2: return k_i8_tiles<2, MODES, PERSIST>;
+        case 3: return k_i8_tiles<3, MODES, PERSIST>;
+        case 4: return k_i8_tiles<4, MODES, PERSIST>;
+        case 5: return k_i8_tiles<5, MODES, PERSIST>;
         default: return nullptr;
     }
 }
 
-hipError_t launch_i8_tiles(int cls, bool noise, const LaunchArgs& a, int grid, hipStream_t s)
+// modes: bit m set if some stream of the launch uses mode m.
+template <bool PERSIST>
+static void (*i8_tile_kernel_p(int cls, int modes))(LaunchArgs)
 {
-    auto k = noise ? i8_tile_kernel<true>(cls) : i8_tile_kernel<false>(cls);
+    switch (modes) {
+        case 1: return i8_tile_kernel_m<1, PERSIST>(cls);
+        case 2: return i8_tile_kernel_m<2, PERSIST>(cls);
+        case 3: return i8_tile_kernel_m<3, PERSIST>(cls);
+        case 4: return i8_tile_kernel_m<4, PERSIST>(cls);
+        default: return i8_tile_kernel_m<7, PERSIST>(cls);
+    }
+}
+
+static void (*i8_tile_kernel(int cls, int modes, bool persist))(LaunchArgs)
+{
+    return persist ? i8_tile_kernel_p<true>(cls, modes) : i8_tile_kernel_p<false>(cls, modes);
+}
+
+hipError_t launch_i8_tiles(int cls, int modes, const LaunchArgs& a, int grid, hipStream_t s)
+{
+    // A grid that covers every item runs the loop-free variant.
+    auto k = i8_tile_kernel(cls, modes, grid < a.n_items);
     if (!k) return hipErrorInvalidValue;
     return launch(k, a, grid, s);
 }
-hipError_t launch_i8_generic(const LaunchArgs& a, int grid, hipStream_t s) { return launch(k_i8_generic, a, grid, s); }
-hipError_t launch_i8_fused(const LaunchArgs& a, int grid, hipStream_t s) { return launch(k_i8_fused, a, grid, s); }
+#define RFI_PICK(K, a, grid) ((grid) < (a).n_items ? K<true> : K<false>)
+hipError_t launch_i8_generic(const LaunchArgs& a, int grid, hipStream_t s)
+{
+    return launch(RFI_PICK(k_i8_generic, a, grid), a, grid, s);
+}
+hipError_t launch_i8_fused(const LaunchArgs& a, int grid, hipStream_t s)
+{
+    return launch(RFI_PICK(k_i8_fused, a, grid), a, grid, s);
+}
 hipError_t launch_i16_tiles(int cls, const LaunchArgs& a, int grid, hipStream_t s)
 {
     if (cls != 0) return hipErrorInvalidValue;
-    return launch(k_i16_tiles, a, grid, s);
+    return launch(RFI_PICK(k_i16_tiles, a, grid), a, grid, s);
 }
-hipError_t launch_i16_generic(const LaunchArgs& a, int grid, hipStream_t s) { return launch(k_i16_generic, a, grid, s); }
-hipError_t launch_i16_fused(const LaunchArgs& a, int grid, hipStream_t s) { return launch(k_i16_fused, a, grid, s); }
+hipError_t launch_i16_generic(const LaunchArgs& a, int grid, hipStream_t s)
+{
+    return launch(RFI_PICK(k_i16_generic, a, grid), a, grid, s);
+}
+hipError_t launch_i16_fused(const LaunchArgs& a, int grid, hipStream_t s)
+{
+    return launch(RFI_PICK(k_i16_fused, a, grid), a, grid, s);
+}
+#undef RFI_PICK
 
-int persistent_grid(int elem_size, int cls, bool noise, bool fused)
+int persistent_grid(int elem_size, int cls, int modes, bool fused)
 {
     void (*k)(LaunchArgs) = nullptr;
     if (elem_size == 1) {
-        if (fused) k = k_i8_fused;
-        else if (cls < 0) k = k_i8_generic;
-        else k = noise ? i8_tile_kernel<true>(cls) : i8_tile_kernel<false>(cls);
+        if (fused) k = k_i8_fused<true>;
+        else if (cls < 0) k = k_i8_generic<true>;
+        else k = i8_tile_kernel(cls, modes, true);
     } else {
-        if (fused) k = k_i16_fused;
-        else if (cls < 0) k = k_i16_generic;
-        else k = k_i16_tiles;
+        if (fused) k = k_i16_fused<true>;
+        else if (cls < 0) k = k_i16_generic<true>;
+        else k = k_i16_tiles<true>;
     }
     int per_cu = 0;
     if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kBlock, 0) != hipSuccess || per_cu < 1)

@@ -1,0 +1,65 @@
+// rfi_ubench.hip -- HBM copy microbenchmark (see rfi_ubench.h).
+#include <hip/hip_runtime.h>
+
+#include "rfi_device.hpp"
+#include "rfi_ubench.h"
+
+namespace rfi {
+
+template <bool NT>
+__global__ __launch_bounds__(256) void k_copy_tile(const uint8_t* __restrict__ x, uint8_t* __restrict__ y)
+{
+    const size_t base = (size_t)blockIdx.x * 16384 + (threadIdx.x >> 6) * 4096 + (threadIdx.x & 63) * 16;
+    uint4 v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if constexpr (NT) {
+            const u32x4 t = __builtin_nontemporal_load((const u32x4*)(x + base + i * 1024));
+            v[i] = make_uint4(t.x, t.y, t.z, t.w);
+        } else {
+            v[i] = gload16(x + base + i * 1024);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if constexpr (NT) {
+            u32x4 t;
+            t.x = v[i].x;
+            t.y = v[i].y;
+            t.z = v[i].z;
+            t.w = v[i].w;
+            __builtin_nontemporal_store(t, (u32x4*)(y + base + i * 1024));
+        } else {
+            gstore16(y + base + i * 1024, v[i]);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_copy_stride(const uint8_t* __restrict__ x, uint8_t* __restrict__ y,
+                                                     size_t n16)
+{
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += (size_t)gridDim.x * 256)
+        gstore16(y + i * 16, gload16(x + i * 16));
+}
+
+}  // namespace rfi
+
+extern "C" int rfi_ubench_copy(const void* x, void* y, uint64_t bytes, int32_t variant, void* stream)
+{
+    if (!x || !y || bytes == 0 || bytes % 16384 != 0 || variant < 0 || variant > 2) return -1;
+    if (((uintptr_t)x | (uintptr_t)y) & 15u) return -2;
+    const uint8_t* xs = static_cast<const uint8_t*>(x);
+    uint8_t* ys = static_cast<uint8_t*>(y);
+    if (xs < ys + bytes && ys < xs + bytes) return -1;
+    hipStream_t s = (hipStream_t)stream;
+    const uint64_t tiles = bytes / 16384;
+    if (tiles > (1u << 30)) return -1;
+    if (variant == 0) hipLaunchKernelGGL(rfi::k_copy_tile<false>, dim3((unsigned)tiles), dim3(256), 0, s, xs, ys);
+    else if (variant == 1) hipLaunchKernelGGL(rfi::k_copy_tile<true>, dim3((unsigned)tiles), dim3(256), 0, s, xs, ys);
+    else {
+        int dev = 0, cus = 256;
+        if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        hipLaunchKernelGGL(rfi::k_copy_stride, dim3((unsigned)(cus * 8)), dim3(256), 0, s, xs, ys, (size_t)(bytes / 16));
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -5;
+}
