@@ -43,6 +43,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the W=16384 variant")
+    ap.add_argument("--with-copy", action="store_true",
+                    help="after timing, run the HBM copy microbenchmark on the same buffers "
+                         "(a kernel of known traffic, to calibrate hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -133,6 +136,11 @@ def main():
                      "kernel": "rfi_i8 window filter, mode %s" % MODE_NAMES[dom],
                      "algorithmic_bytes_per_launch": abytes},
     }
+
+    if args.with_copy:
+        for _ in range(args.steps):
+            rfi._lib.ubench_copy(x, y, 1)
+        torch.cuda.synchronize()
 
     # W = 16384 variant of the same workload (context, not the headline).
     if not args.no_extra:

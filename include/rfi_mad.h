@@ -22,9 +22,10 @@
  *       RFI_MODE_NOISE  saturate(median + q), q = (s * G[u] + 2^15) >> 16
  *                       (arithmetic shift), s = (int)(1.4826f*D * 256.0f),
  *                       G[u] = round(256 * PhiInv((u + 0.5) / 4096)),
- *                       u = top 12 bits of word (j & 3) of the
- *                       Philox4x64-10 block (Salmon et al., SC'11) with
- *                       key (seed, stream) and counter (j >> 2, 0, 0, 0),
+ *                       u = bits [63 - 12c, 52 - 12c] (c = j & 3) of word
+ *                       (j >> 2) & 3 of the Philox4x64-10 block (Salmon
+ *                       et al., SC'11) with key (seed, stream) and counter
+ *                       (j >> 4, 0, 0, 0): one block per 16 samples;
  *                       j = absolute sample index within the stream.
  *   - statistics are taken from the input window in every mode.
  *
@@ -151,6 +152,15 @@ int rfi_plan_get_schedule(const rfi_plan* plan);
 int rfi_plan_set_graph(rfi_plan* plan, int32_t use_graph);
 int rfi_plan_execute(rfi_plan* plan, const void* x, void* y, rfi_window_stats* stats_out,
                      void* stream);
+/* Plan options.
+ *   RFI_OPT_TILES_PER_WG  int8 tiles (16 KiB) per workgroup in launches with
+ *                         one workgroup per item: 1, 2 (the second tile's
+ *                         loads overlap the first tile's work) or 0 (use
+ *                         the autotuned value, default 1).
+ *   RFI_OPT_WG_PER_CU     at most this many workgroups resident per compute
+ *                         unit (1..32, enforced by padding LDS), 0 = no cap. */
+typedef enum { RFI_OPT_TILES_PER_WG = 1, RFI_OPT_WG_PER_CU = 2 } rfi_option;
+int rfi_plan_set_option(rfi_plan* plan, int32_t option, int32_t value);
 /* Number of kernel launches one execute makes, and total windows. */
 int rfi_plan_info(const rfi_plan* plan, int32_t* n_launches, int64_t* n_windows,
                   int64_t* n_tiles, int64_t* n_generic);

@@ -22,8 +22,9 @@
  *   - "threshold" replacement is m +/- floor(t), saturated to the dtype;
  *   - "constant" replacement is 0 (every experiment in Sec. III uses zeros);
  *   - "digital noise" is m + q, q drawn from a Q8 Gaussian quantile table
- *     scaled by the robust sigma, indexed by Philox4x64-10 (Salmon et al.,
- *     SC'11) keyed by (seed, stream) at the absolute sample index;
+ *     scaled by the robust sigma, indexed by a 12-bit field of a
+ *     Philox4x64-10 block (Salmon et al., SC'11) keyed by (seed, stream);
+ *     one block per 16 consecutive samples at absolute index j >> 4;
  *   - a short final window is a window of its own.
  */
 #ifndef RFI_ORACLE_H

@@ -59,6 +59,7 @@ _SIGS = {
     "rfi_plan_set_schedule": (ctypes.c_int, [P, I32]),
     "rfi_plan_get_schedule": (ctypes.c_int, [P]),
     "rfi_plan_set_graph": (ctypes.c_int, [P, I32]),
+    "rfi_plan_set_option": (ctypes.c_int, [P, I32, I32]),
     "rfi_plan_execute": (ctypes.c_int, [P, P, P, P, P]),
     "rfi_plan_info": (ctypes.c_int, [P, P, P, P, P]),
     "rfi_plan_autotune": (ctypes.c_int, [P, P, P, P, P, I32, P, P]),
@@ -210,6 +211,12 @@ class Plan:
 
     def schedule(self) -> int:
         return load().rfi_plan_get_schedule(self.h)
+
+    def set_tiles_per_wg(self, tpw: int):
+        _check(load().rfi_plan_set_option(self.h, 1, int(tpw)), "rfi_plan_set_option")
+
+    def set_wg_per_cu(self, n: int):
+        _check(load().rfi_plan_set_option(self.h, 2, int(n)), "rfi_plan_set_option")
 
     def set_graph(self, on: bool):
         _check(load().rfi_plan_set_graph(self.h, 1 if on else 0), "rfi_plan_set_graph")

@@ -51,6 +51,7 @@ static std::mutex g_tune_mu;
 static std::map<uint64_t, int> g_tune;
 
 uint64_t plan_signature(const rfi_plan* p);
+int tuned_tpw(uint64_t sig);
 
 int tuned_schedule(uint64_t sig)
 {
@@ -63,6 +64,21 @@ void record_schedule(uint64_t sig, int sched)
 {
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune[sig] = sched;
+}
+
+static std::map<uint64_t, int> g_tune_tpw;
+
+int tuned_tpw(uint64_t sig)
+{
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune_tpw.find(sig);
+    return it == g_tune_tpw.end() ? 1 : it->second;
+}
+
+void record_tpw(uint64_t sig, int tpw)
+{
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune_tpw[sig] = tpw;
 }
 
 }  // namespace rfi
@@ -82,6 +98,7 @@ struct GraphEntry {
     uint64_t x, y, st;
     hipStream_t s;
     int sched;
+    int tpw;
     hipGraph_t graph;
     hipGraphExec_t exec;
 };
@@ -102,6 +119,8 @@ struct rfi_plan {
     int64_t n_windows = 0, n_tiles = 0, n_generic = 0;
     int schedule = RFI_SCHED_AUTO;
     int use_graph = 0;
+    int tpw = 0;  // int8 tiles per workgroup in loop-free launches (0: tuned)
+    int wg_per_cu = 0;  // occupancy cap (0: none)
     std::vector<PlanLaunch> launches[RFI_SCHED_COUNT];
     std::vector<GraphEntry> graphs;
 };
@@ -126,11 +145,12 @@ static int tile_class(int elem, int32_t w) { return elem == 1 ? i8_tile_class(w)
 static hipError_t run_launch(const rfi_plan* p, const PlanLaunch& l, const LaunchArgs& base,
                              hipStream_t s)
 {
+    set_wg_per_cu(p->wg_per_cu);
     LaunchArgs a = base;
     a.items = p->ditems + l.first;
     a.n_items = l.count;
     if (p->elem == 1) {
-        if (l.kind == 0) return launch_i8_tiles(l.cls, l.modes, a, l.grid, s);
+        if (l.kind == 0) return launch_i8_tiles(l.cls, l.modes, p->tpw > 0 ? p->tpw : tuned_tpw(plan_signature(p)), a, l.grid, s);
         if (l.kind == 1) return launch_i8_generic(a, l.grid, s);
         return launch_i8_fused(a, l.grid, s);
     }
@@ -311,7 +331,7 @@ int plan_execute(rfi_plan* p, const void* x, void* y, rfi_window_stats* st, hipS
     if (p->use_graph && s != nullptr && !ls.empty()) {
         for (auto& g : p->graphs) {
             if (g.x == base.x_base && g.y == base.y_base && g.st == base.stats_base && g.s == s &&
-                g.sched == sched) {
+                g.sched == sched && g.tpw == p->tpw) {
                 hipError_t e = hipGraphLaunch(g.exec, s);
                 return e == hipSuccess ? RFI_OK : hip_fail(e);
             }
@@ -322,7 +342,7 @@ int plan_execute(rfi_plan* p, const void* x, void* y, rfi_window_stats* st, hipS
             (void)hipGraphDestroy(p->graphs.front().graph);
             p->graphs.erase(p->graphs.begin());
         }
-        GraphEntry g{base.x_base, base.y_base, base.stats_base, s, sched, nullptr, nullptr};
+        GraphEntry g{base.x_base, base.y_base, base.stats_base, s, sched, p->tpw, nullptr, nullptr};
         hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e);
         hipError_t le = hipSuccess;
@@ -445,6 +465,24 @@ int rfi_plan_set_graph(rfi_plan* plan, int32_t use_graph)
     return RFI_OK;
 }
 
+int rfi_plan_set_option(rfi_plan* plan, int32_t option, int32_t value)
+{
+    if (!plan) return RFI_ERR_INVALID;
+    if (option == RFI_OPT_TILES_PER_WG) {
+        if (value < 0 || value > 2) return RFI_ERR_INVALID;
+        plan->tpw = value;
+        drop_graphs(plan);
+        return RFI_OK;
+    }
+    if (option == RFI_OPT_WG_PER_CU) {
+        if (value < 0 || value > 32) return RFI_ERR_INVALID;
+        plan->wg_per_cu = value;
+        drop_graphs(plan);
+        return RFI_OK;
+    }
+    return RFI_ERR_INVALID;
+}
+
 int rfi_plan_execute(rfi_plan* plan, const void* x, void* y, rfi_window_stats* stats_out,
                      void* stream)
 {
@@ -476,12 +514,16 @@ int rfi_plan_autotune(rfi_plan* plan, const void* x, void* y, rfi_window_stats* 
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return hip_fail(hipGetLastError());
-    int best = RFI_SCHED_SPLIT;
+    int best = RFI_SCHED_SPLIT, best_tpw = 1;
     float best_t = 1e30f;
-    const int cands[] = {RFI_SCHED_SPLIT, RFI_SCHED_SPLIT_PERSIST, RFI_SCHED_FUSED,
-                         RFI_SCHED_FUSED_PERSIST};
-    for (int c : cands) {
+    const int saved_tpw = plan->tpw;
+    struct Cand { int sched, tpw; };
+    const Cand cands[] = {{RFI_SCHED_SPLIT, 2}, {RFI_SCHED_SPLIT, 1}, {RFI_SCHED_SPLIT_PERSIST, 1},
+                          {RFI_SCHED_FUSED, 1}, {RFI_SCHED_FUSED_PERSIST, 1}};
+    for (const Cand& cand : cands) {
+        const int c = cand.sched;
         if (plan->launches[c].empty()) continue;
+        plan->tpw = cand.tpw;
         rc = plan_execute(plan, x, y, stats_out, s, c);  // warm-up (graph capture)
         if (rc != RFI_OK) break;
         std::vector<float> ts;
@@ -501,13 +543,17 @@ int rfi_plan_autotune(rfi_plan* plan, const void* x, void* y, rfi_window_stats* 
         if (med < best_t) {
             best_t = med;
             best = c;
+            best_tpw = cand.tpw;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    plan->tpw = saved_tpw;
     if (rc != RFI_OK) return rc;
     plan->schedule = best;
+    plan->tpw = best_tpw;
     record_schedule(plan_signature(plan), best);
+    record_tpw(plan_signature(plan), best_tpw);
     if (best_schedule) *best_schedule = best;
     if (best_ms) *best_ms = best_t;
     return RFI_OK;

@@ -215,18 +215,61 @@ __device__ __forceinline__ uint32_t clamp_i8x4(uint32_t x, uint32_t lo256, uint3
     return oc | (ec >> 8);
 }
 
+typedef unsigned short ushort2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t pk_usubsat(uint32_t a, uint32_t b)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_sub_sat(__builtin_bit_cast(ushort2v, a),
+                                                                      __builtin_bit_cast(ushort2v, b)));
+}
+
+// min(a, 1) in both unsigned 16-bit halves, as one v_pk_min_u16 (the
+// generic form is split by the compiler into per-half compares).  The
+// constant 0x00010001 comes from a scalar register: an inline constant in a
+// packed instruction would feed only the low half.
+__device__ __forceinline__ uint32_t pk_umin1(uint32_t a)
+{
+    uint32_t r;
+    asm volatile("v_pk_min_u16 %0, %1, %2" : "=v"(r) : "v"(a), "s"(0x00010001u));
+    return r;
+}
+
+// Byte-permute selector of the int8 samples of x outside [lo, hi]: byte k
+// of the result is k for a kept sample and k + 4 for a flagged one, so
+// v_perm_b32(other, x, sel) takes flagged bytes from `other` (0 for zeroing,
+// noise bytes for noise).  lo_u / hi_u: (lo + 128) << 8 and (hi + 128) << 8
+// in both 16-bit halves.  The bytes are biased to unsigned and moved to the
+// high byte of 16-bit lanes; a saturating subtract is non-zero exactly when
+// a bound is crossed.
+__device__ __forceinline__ uint32_t flag_sel_i8x4(uint32_t x, uint32_t lo_u, uint32_t hi_u)
+{
+    const uint32_t xb = x ^ 0x80808080u;
+    const uint32_t odd = xb & 0xFF00FF00u;          // bytes 1, 3
+    const uint32_t even = (xb << 8) & 0xFF00FF00u;  // bytes 0, 2
+    const uint32_t fo = pk_umin1(pk_usubsat(lo_u, odd) | pk_usubsat(odd, hi_u));
+    const uint32_t fe = pk_umin1(pk_usubsat(lo_u, even) | pk_usubsat(even, hi_u));
+    return 0x03020100u | (fo << 10) | (fe << 2);
+}
+
+__device__ __forceinline__ uint32_t byte_perm(uint32_t hi_src, uint32_t lo_src, uint32_t sel)
+{
+    return __builtin_amdgcn_perm(hi_src, lo_src, sel);
+}
+
 // 0xFF in every byte of `diff` that is non-zero, 0x00 elsewhere.
 __device__ __forceinline__ uint32_t nonzero_byte_mask(uint32_t diff)
 {
     const uint32_t h = (((diff & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | diff) & 0x80808080u;
-    return (h >> 7) * 0xFFu;
+    // 0x80 -> 0xFF per byte: (0x80 << 1) - (0x80 >> 7) = 0xFF, modulo 2^32 at
+    // the top byte (no full-width multiply).
+    return (h << 1) - (h >> 7);
 }
 
 // 0xFFFF in every 16-bit half of `diff` that is non-zero.
 __device__ __forceinline__ uint32_t nonzero_half_mask(uint32_t diff)
 {
     const uint32_t h = (((diff & 0x7FFF7FFFu) + 0x7FFF7FFFu) | diff) & 0x80008000u;
-    return (h >> 15) * 0xFFFFu;
+    return (h << 1) - (h >> 15);
 }
 
 __device__ __forceinline__ uint32_t rep_i16(int v)

@@ -116,12 +116,15 @@ __host__ __device__ inline StreamView resolve(const StreamDesc& d, const LaunchA
 // Host wrappers around the kernels (defined in rfi_kernels.hip).
 // cls: tile class (-1 = generic items); modes: bit m set if mode m occurs;
 // fused: one kernel for all kinds.
-hipError_t launch_i8_tiles(int cls, int modes, const LaunchArgs& a, int grid, hipStream_t s);
+hipError_t launch_i8_tiles(int cls, int modes, int tpw, const LaunchArgs& a, int grid, hipStream_t s);
 hipError_t launch_i8_generic(const LaunchArgs& a, int grid, hipStream_t s);
 hipError_t launch_i8_fused(const LaunchArgs& a, int grid, hipStream_t s);
 hipError_t launch_i16_tiles(int cls, const LaunchArgs& a, int grid, hipStream_t s);
 hipError_t launch_i16_generic(const LaunchArgs& a, int grid, hipStream_t s);
 hipError_t launch_i16_fused(const LaunchArgs& a, int grid, hipStream_t s);
+
+// Occupancy cap for the launches issued by this thread (0: none).
+void set_wg_per_cu(int n);
 
 // Occupancy-derived persistent grid size for a kernel choice.
 int persistent_grid(int elem_size, int cls, int modes, bool fused);

@@ -56,7 +56,7 @@ __device__ __forceinline__ float threshold_of(int D, float k, float& sig)
 // int8: selection from a 256-bin histogram owned by an aligned group of G
 // lanes (G = 8..64, 256 / G bins per lane).  On return the bins hold
 // inclusive cumulative counts and every lane of the group has mb (median
-// + 128) and D.
+// + 128) and D.  Used when a wave holds several windows.
 // ---------------------------------------------------------------------------
 template <int G>
 __device__ __forceinline__ void select_i8(uint32_t* hw, uint32_t need, int& mb, int& D)
@@ -125,83 +125,236 @@ __device__ __forceinline__ void params_i8(const uint32_t* hw, int mb, int D, flo
 }
 
 // ---------------------------------------------------------------------------
-// Noise for flagged dwords of one wave (16 dwords per lane, bit q of `fl`
-// marks dword q).  The owner lanes publish (lane, q) entries; each lane
-// draws the noise dword of entries lane, lane + 64, ...; owners merge.
-// dword_noise(owner, q) returns the packed replacement dword; mask_of(q)
-// returns the byte/half mask of flagged samples in v[q].
-// scratch: 512 words of LDS private to this wave.
+// Wide windows (W >= 4096, whole waves per window).  Each wave keeps four
+// replicas of a 256-bin histogram (lane & 3 picks one; replicas start eight
+// banks apart, which spreads same-bin atomics of a wave), indexed by the raw
+// byte so a sample costs one bit-field extract and one address add.
 // ---------------------------------------------------------------------------
-template <class NoiseFn, class MaskFn>
-__device__ __forceinline__ void merge_noise(uint32_t (&v)[16], uint32_t fl, uint32_t* scratch,
-                                            NoiseFn dword_noise, MaskFn mask_of)
+constexpr int kRepStride = 264;                // 256 bins + 8 words
+constexpr int kWaveHistWords = 4 * kRepStride;  // per wave
+// Padded cumulative array: pc[0..3] = 0 (C[-4..-1]), pc[4 + v] = C[v] for
+// the biased value v = 0..255, pc[260..263] = N.
+constexpr int kPadC = 264;
+
+__device__ __forceinline__ void wide_hist_zero(uint32_t* h)
 {
     const int lane = lane_id();
-    uint32_t* list = scratch;
-    uint32_t* stage = scratch + 256;
-    const uint32_t cnt = __popc(fl);
+    uint4* p = reinterpret_cast<uint4*>(h);
+#pragma unroll
+    for (int i = 0; i < (kWaveHistWords / 4 + 63) / 64; ++i) {
+        const int idx = i * 64 + lane;
+        if (idx < kWaveHistWords / 4) p[idx] = make_uint4(0, 0, 0, 0);
+    }
+}
+
+// hl: this lane's replica.
+__device__ __forceinline__ void wide_hist_add(uint32_t* hl, uint32_t x)
+{
+    atomicAdd(hl + (x & 0xFFu), 1u);
+    atomicAdd(hl + ((x >> 8) & 0xFFu), 1u);
+    atomicAdd(hl + ((x >> 16) & 0xFFu), 1u);
+    atomicAdd(hl + (x >> 24), 1u);
+}
+
+// Counts of the biased bins 4*lane .. 4*lane+3 (biased bin v holds the raw
+// byte (v + 128) & 255), summed over the four replicas.
+__device__ __forceinline__ void wide_hist_totals(const uint32_t* h, uint32_t (&c)[4])
+{
+    const int rb = (4 * lane_id() + 128) & 255;
+    c[0] = c[1] = c[2] = c[3] = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const uint4 t = *reinterpret_cast<const uint4*>(h + r * kRepStride + rb);
+        c[0] += t.x;
+        c[1] += t.y;
+        c[2] += t.z;
+        c[3] += t.w;
+    }
+}
+
+// Selection over a whole wave holding the counts of bins 4*lane.. in c:
+// writes the padded cumulative array pc and returns the wave-uniform mb
+// (median + 128) and D.  The padding lets every lane read four consecutive
+// counts without clamping its indices.
+__device__ __forceinline__ void wide_select(uint32_t (&c)[4], uint32_t* pc, uint32_t need, int& mb,
+                                            int& D)
+{
+    const int lane = lane_id();
+    c[1] += c[0];
+    c[2] += c[1];
+    c[3] += c[2];
+    const uint32_t incl = group_incl_scan<64>(c[3]);
+    const uint32_t excl = incl - c[3];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) c[j] += excl;
+    *reinterpret_cast<uint4*>(pc + 4 + 4 * lane) = make_uint4(c[0], c[1], c[2], c[3]);
+    if (lane == 0) *reinterpret_cast<uint4*>(pc) = make_uint4(0, 0, 0, 0);
+    if (lane == 63) *reinterpret_cast<uint4*>(pc + 260) = make_uint4(c[3], c[3], c[3], c[3]);
+    int below = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) below += group_count<64>(c[j] < need);
+    mb = below;
+    wave_sync();
+    // d = 4*lane + j: C[min(mb + d, 255)] - C[mb - d - 1]
+    const int t = min(mb + 4 * lane, 255) + 4;
+    const int s = max(mb - 4 * lane - 1, -1) + 4;
+    int dbelow = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) dbelow += group_count<64>(pc[t + j] - pc[s - j] < need);
+    D = dbelow;
+}
+
+__device__ __forceinline__ void wide_params(const uint32_t* pc, int mb, int D, float k, int n,
+                                            WinParams& p, rfi_window_stats& s)
+{
+    float sig;
+    const float t = threshold_of(D, k, sig);
+    const int T = (int)floorf(t);
+    const int m = mb - 128;
+    const int lo = max(m - T, -128), hi = min(m + T, 127);
+    const uint32_t inside = pc[4 + hi + 128] - pc[3 + lo + 128];
+    p.lo = lo;
+    p.hi = hi;
+    p.m = m;
+    p.sq8 = (int)__fmul_rn(sig, 256.0f);
+    s.median = m;
+    s.mad = D;
+    s.n_flagged = (uint32_t)n - inside;
+    s.threshold = t;
+}
+
+// ---------------------------------------------------------------------------
+// Noise.  One Philox4x64-10 block serves 16 consecutive samples: word
+// (j >> 2) & 3 holds four 12-bit fields, most significant first, and sample
+// j takes field j & 3.  A 16-byte chunk of int8 samples is one block.
+// ---------------------------------------------------------------------------
+// 16 int8 noise samples for the chunk whose first absolute index is j0
+// (a multiple of 16): byte c of word w is sample 4w + c.
+__device__ __forceinline__ uint4 noise_chunk_i8(uint64_t j0, uint64_t seed, uint32_t key, int m,
+                                                int sq8)
+{
+    const Philox4x64 r = philox4x64_10(j0 >> 4, seed, key);
+    uint32_t o[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        uint32_t nb = 0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int g = c_q8[(uint32_t)(r.w[w] >> (52 - 12 * c)) & 0xFFFu];
+            const int q = (sq8 * g + 32768) >> 16;  // |sq8 * g| < 2^31 for int8
+            nb |= ((uint32_t)min(max(m + q, -128), 127) & 0xFFu) << (8 * c);
+        }
+        o[w] = nb;
+    }
+    return make_uint4(o[0], o[1], o[2], o[3]);
+}
+
+// Flagged 16-byte chunks of a workgroup's tile are pooled into one list;
+// each list entry is turned into its merged chunk (noise in the flagged
+// samples) by one thread, so the Philox draws of a workgroup occupy as few
+// waves as the list needs.  cf bit i: slot i of this lane is flagged;
+// merged(wave, lane, slot, x) returns the merged chunk.
+struct NoiseScratch {
+    uint32_t list[256];
+    uint4 data[256];
+    uint32_t counts[4];
+};
+
+template <class ChunkFn>
+__device__ __forceinline__ void pool_noise(uint32_t (&v)[16], uint32_t cf, NoiseScratch& ns,
+                                           ChunkFn merged)
+{
+    const int lane = lane_id();
+    const int wave = (int)(threadIdx.x >> 6);
+    const uint32_t cnt = __popc(cf);
     const uint32_t incl = group_incl_scan<64>(cnt);
-    const int base = (int)(incl - cnt);
-    const int F = __builtin_amdgcn_readlane((int)incl, 63);
+    if (lane == 63) ns.counts[wave] = incl;
+    __syncthreads();
+    int wbase = 0, F = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const int c = (int)ns.counts[w];
+        wbase += w < wave ? c : 0;
+        F += c;
+    }
+    const int base = wbase + (int)(incl - cnt);
+    // With no entries the loop below has no barrier: close the counts reads
+    // here so no wave reuses the scratch while another still reads it.
+    if (F == 0) __syncthreads();
     for (int r0 = 0; r0 < F; r0 += 256) {
         int e = base - r0;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            if ((fl >> q) & 1u) {
-                if (e >= 0 && e < 256) list[e] = (uint32_t)(lane << 4 | q);
-                ++e;
-            }
-            sched_fence();
-        }
-        wave_sync();
-        const int nE = min(256, F - r0);
-        for (int i = lane; i < nE; i += 64) {
-            const uint32_t ent = list[i];
-            stage[i] = dword_noise((int)(ent >> 4), (int)(ent & 15u));
-        }
-        wave_sync();
-        e = base - r0;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            if ((fl >> q) & 1u) {
+        for (int i = 0; i < 4; ++i) {
+            if ((cf >> i) & 1u) {
                 if (e >= 0 && e < 256) {
-                    const uint32_t mk = mask_of(q);
-                    v[q] = (v[q] & ~mk) | (stage[e] & mk);
+                    ns.list[e] = (uint32_t)(wave << 8 | lane << 2 | i);
+                    ns.data[e] = make_uint4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]);
                 }
                 ++e;
             }
-            sched_fence();
         }
-        wave_sync();
+        __syncthreads();
+        const int k = (int)threadIdx.x;
+        if (k < min(256, F - r0)) {
+            const uint32_t ent = ns.list[k];
+            ns.data[k] = merged((int)(ent >> 8), (int)((ent >> 2) & 63u), (int)(ent & 3u), ns.data[k]);
+        }
+        __syncthreads();
+        e = base - r0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if ((cf >> i) & 1u) {
+                if (e >= 0 && e < 256) {
+                    const uint4 t = ns.data[e];
+                    v[4 * i] = t.x;
+                    v[4 * i + 1] = t.y;
+                    v[4 * i + 2] = t.z;
+                    v[4 * i + 3] = t.w;
+                }
+                ++e;
+            }
+        }
+        __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------
-// int8 tile: 16 KiB of whole windows of one class W, 64 bytes per lane.
+// int8 tiles: 16 KiB of whole windows of one class W, 64 bytes per lane.
 // ---------------------------------------------------------------------------
-template <int W, bool NOISE>
+template <int W, bool NS>
 struct I8TileSmem {
     static constexpr int kWin = 16384 / W;
-    uint32_t hist[kWin * 256];
+    static constexpr bool kWide = W >= 4096;
+    static constexpr int kWPW = kWide ? W / 4096 : 1;  // waves per window
+    // wide: per-wave replicated histograms; W = 4096 keeps its cumulative
+    // counts in replica 0 of its wave, larger W in pc.
+    uint32_t hist[kWide ? 4 * kWaveHistWords : kWin * 256];
+    uint32_t tot[kWPW > 1 ? kWin * 256 : 0];
+    uint32_t pc[kWPW > 1 ? kWin * kPadC : 0];
     WinParams prm[kWin];
-    uint32_t noise[NOISE ? 4 * 512 : 1];
+    NoiseScratch ns[NS ? 1 : 0];
 };
 
-template <int W, bool NOISE, int MODE>
-__device__ __forceinline__ void i8_tile(const StreamView& d, int64_t first, uint64_t seed,
-                                        I8TileSmem<W, NOISE>& sm)
-{
-    static_assert(MODE != RFI_MODE_NOISE || NOISE, "noise needs its LDS scratch");
-    constexpr int NWW = W < 4096 ? 4096 / W : 1;  // windows per wave
-    constexpr int WPW = W > 4096 ? W / 4096 : 1;  // waves per window
-    constexpr int G = 64 / NWW;                   // lanes per window in the scan
-    const int lane = lane_id();
-    const int wave = (int)(threadIdx.x >> 6);
-    const int wbase = wave * 4096;
-    const uint8_t* xt = static_cast<const uint8_t*>(d.x) + first + wbase + lane * 16;
-    uint8_t* yt = static_cast<uint8_t*>(d.y) + first + wbase + lane * 16;
+// Statistics record of one window produced by a tile, written by the caller
+// once the tile's samples are stored.
+struct TileStats {
+    rfi_window_stats s;
+    rfi_window_stats* dst;  // NULL: this lane writes nothing
+};
 
-    uint32_t v[16];
+__device__ __forceinline__ void write_stats(const TileStats& t)
+{
+    if (t.dst)
+        gstore16(t.dst, make_uint4((uint32_t)t.s.median, (uint32_t)t.s.mad, t.s.n_flagged,
+                                   __float_as_uint(t.s.threshold)));
+}
+
+// This lane's 64 bytes of a 16 KiB tile: four 16-byte loads at a 1 KiB
+// stride, so each load instruction of the wave covers 1 KiB contiguously.
+__device__ __forceinline__ void tile_load(const StreamView& d, int64_t first_byte, uint32_t (&v)[16])
+{
+    const uint8_t* xt = static_cast<const uint8_t*>(d.x) + first_byte + (threadIdx.x >> 6) * 4096 +
+                        lane_id() * 16;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const uint4 t = gload16_nt(xt + i * 1024);
@@ -210,73 +363,18 @@ __device__ __forceinline__ void i8_tile(const StreamView& d, int64_t first, uint
         v[4 * i + 2] = t.z;
         v[4 * i + 3] = t.w;
     }
+}
 
-    // Zero the histograms this wave (or workgroup) owns.
-    if constexpr (WPW == 1) {
-        uint4* h = reinterpret_cast<uint4*>(sm.hist + wave * NWW * 256);
-#pragma unroll
-        for (int j = 0; j < NWW; ++j) h[j * 64 + lane] = make_uint4(0, 0, 0, 0);
-        wave_sync();
-    } else {
-        __syncthreads();
-        if (threadIdx.x < (16384 / W) * 64)
-            reinterpret_cast<uint4*>(sm.hist)[threadIdx.x] = make_uint4(0, 0, 0, 0);
-        __syncthreads();
-    }
-
-    // Histogram of x + 128 (the byte xor 0x80).
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        uint32_t* h = sm.hist + ((wbase + i * 1024 + lane * 16) / W) * 256;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint32_t u = v[4 * i + j] ^ 0x80808080u;
-            atomicAdd(&h[u & 0xFFu], 1u);
-            atomicAdd(&h[(u >> 8) & 0xFFu], 1u);
-            atomicAdd(&h[(u >> 16) & 0xFFu], 1u);
-            atomicAdd(&h[u >> 24], 1u);
-            sched_fence();
-        }
-    }
-
-    constexpr uint32_t need = (W - 1) / 2 + 1;
-    if constexpr (WPW == 1) {
-        wave_sync();
-        const int wl = wave * NWW + lane / G;
-        uint32_t* hw = sm.hist + wl * 256;
-        int mb, D;
-        select_i8<G>(hw, need, mb, D);
-        WinParams p;
-        rfi_window_stats s;
-        params_i8(hw, mb, D, d.k, W, p, s);
-        if ((lane & (G - 1)) == 0) {
-            sm.prm[wl] = p;
-            if (d.stats) d.stats[first / W + wl] = s;
-        }
-        wave_sync();
-    } else {
-        __syncthreads();
-        if (wave % WPW == 0) {
-            const int wl = wave / WPW;
-            uint32_t* hw = sm.hist + wl * 256;
-            int mb, D;
-            select_i8<64>(hw, need, mb, D);
-            WinParams p;
-            rfi_window_stats s;
-            params_i8(hw, mb, D, d.k, W, p, s);
-            if (lane == 0) {
-                sm.prm[wl] = p;
-                if (d.stats) d.stats[first / W + wl] = s;
-            }
-        }
-        __syncthreads();
-    }
-
-    // Replacement (Eq. (2)).
+// Replacement of one lane's 16 dwords.  bounds(i) returns the window
+// parameters of load slot i.  NOISE needs the pooled scratch.
+template <int W, bool NS, int MODE, class Bounds>
+__device__ __forceinline__ void i8_replace(const StreamView& d, int64_t first, uint64_t seed,
+                                           I8TileSmem<W, NS>& sm, uint32_t (&v)[16], Bounds bounds)
+{
     if constexpr (MODE == RFI_MODE_CLIP) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const WinParams p = sm.prm[(wbase + i * 1024 + lane * 16) / W];
+            const WinParams p = bounds(i);
             const uint32_t lo = rep_i16(p.lo * 256), hi = rep_i16(p.hi * 256);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -287,74 +385,177 @@ __device__ __forceinline__ void i8_tile(const StreamView& d, int64_t first, uint
     } else if constexpr (MODE == RFI_MODE_ZERO) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const WinParams p = sm.prm[(wbase + i * 1024 + lane * 16) / W];
-            const uint32_t lo = rep_i16(p.lo * 256), hi = rep_i16(p.hi * 256);
+            const WinParams p = bounds(i);
+            const uint32_t lo_u = rep_i16((p.lo + 128) * 256), hi_u = rep_i16((p.hi + 128) * 256);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const uint32_t x = v[4 * i + j];
-                v[4 * i + j] = x & ~nonzero_byte_mask(clamp_i8x4(x, lo, hi) ^ x);
+                v[4 * i + j] = byte_perm(0u, v[4 * i + j], flag_sel_i8x4(v[4 * i + j], lo_u, hi_u));
                 sched_fence();
             }
         }
     } else {
-        uint32_t fl = 0;
+        static_assert(NS, "noise needs its LDS scratch");
+        uint32_t cf = 0;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const WinParams p = sm.prm[(wbase + i * 1024 + lane * 16) / W];
+            const WinParams p = bounds(i);
             const uint32_t lo = rep_i16(p.lo * 256), hi = rep_i16(p.hi * 256);
+            uint32_t t = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) t |= clamp_i8x4(v[4 * i + j], lo, hi) ^ v[4 * i + j];
+            cf |= (t != 0 ? 1u : 0u) << i;
+            sched_fence();
+        }
+        if constexpr (NS) {
+            const int64_t abs0 = d.abs_base + first;
+            const uint32_t key1 = d.key;
+            auto merged = [&](int wv, int ln, int slot, uint4 x) -> uint4 {
+                const int off = wv * 4096 + slot * 1024 + ln * 16;
+                const WinParams p = sm.prm[off / W];
+                const uint32_t lo_u = rep_i16((p.lo + 128) * 256), hi_u = rep_i16((p.hi + 128) * 256);
+                const uint4 nz = noise_chunk_i8((uint64_t)(abs0 + off), seed, key1, p.m, p.sq8);
+                return make_uint4(byte_perm(nz.x, x.x, flag_sel_i8x4(x.x, lo_u, hi_u)),
+                                  byte_perm(nz.y, x.y, flag_sel_i8x4(x.y, lo_u, hi_u)),
+                                  byte_perm(nz.z, x.z, flag_sel_i8x4(x.z, lo_u, hi_u)),
+                                  byte_perm(nz.w, x.w, flag_sel_i8x4(x.w, lo_u, hi_u)));
+            };
+            pool_noise(v, cf, sm.ns[0], merged);
+        }
+    }
+}
+
+// Processes one int8 tile whose samples this lane already holds in v
+// (tile_load), stores the output, and returns the statistics record this
+// lane must write (see write_stats).
+template <int W, bool NS, int MODE>
+__device__ __forceinline__ TileStats i8_tile(const StreamView& d, int64_t first, uint64_t seed,
+                                             I8TileSmem<W, NS>& sm, uint32_t (&v)[16])
+{
+    using Smem = I8TileSmem<W, NS>;
+    constexpr uint32_t need = (W - 1) / 2 + 1;
+    const int lane = lane_id();
+    const int wave = (int)(threadIdx.x >> 6);
+    const int wbase = wave * 4096;
+    TileStats ts;
+    ts.dst = nullptr;
+
+    if constexpr (Smem::kWide) {
+        constexpr int WPW = Smem::kWPW;
+        const int wl = wave / WPW;
+        uint32_t* h = sm.hist + wave * kWaveHistWords;
+        if constexpr (WPW > 1) {
+            __syncthreads();  // the previous tile is done with tot, pc and prm
+            if (threadIdx.x < Smem::kWin * 64)
+                reinterpret_cast<uint4*>(sm.tot)[threadIdx.x] = make_uint4(0, 0, 0, 0);
+        }
+        wide_hist_zero(h);
+        wave_sync();
+        uint32_t* hl = h + (lane & 3) * kRepStride;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            wide_hist_add(hl, v[q]);
+            sched_fence();
+        }
+        wave_sync();
+        uint32_t c[4];
+        wide_hist_totals(h, c);
+        // W = 4096: the cumulative counts overwrite replica 0 of this wave,
+        // whose reads were all issued above.
+        uint32_t* pc = WPW == 1 ? h : sm.pc + wl * kPadC;
+        int mb = 0, D = 0;
+        if constexpr (WPW == 1) {
+            wide_select(c, pc, need, mb, D);
+        } else {
+            __syncthreads();  // tot is zero everywhere
+#pragma unroll
+            for (int j = 0; j < 4; ++j) atomicAdd(&sm.tot[wl * 256 + lane * 4 + j], c[j]);
+            __syncthreads();
+            if (wave % WPW == 0) {
+                const uint4 t = *reinterpret_cast<const uint4*>(sm.tot + wl * 256 + lane * 4);
+                c[0] = t.x;
+                c[1] = t.y;
+                c[2] = t.z;
+                c[3] = t.w;
+                wide_select(c, pc, need, mb, D);
+            }
+        }
+        WinParams p;
+        if (wave % WPW == 0) {
+            rfi_window_stats ws;
+            wide_params(pc, mb, D, d.k, W, p, ws);
+            if (lane == 0) sm.prm[wl] = p;
+            ts.s = ws;
+            ts.dst = (lane == 0 && d.stats) ? d.stats + first / W + wl : nullptr;
+        }
+        if constexpr (WPW > 1) {
+            __syncthreads();
+            p = sm.prm[wl];
+        }
+        i8_replace<W, NS, MODE>(d, first, seed, sm, v, [&](int) { return p; });
+    } else {
+        // Several windows per wave: one 256-bin histogram of x + 128 per window.
+        constexpr int NWW = 4096 / W;  // windows per wave
+        constexpr int G = 64 / NWW;    // lanes per window in the scan
+        uint4* h0 = reinterpret_cast<uint4*>(sm.hist + wave * NWW * 256);
+#pragma unroll
+        for (int j = 0; j < NWW; ++j) h0[j * 64 + lane] = make_uint4(0, 0, 0, 0);
+        wave_sync();
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            uint32_t* hh = sm.hist + ((wbase + i * 1024 + lane * 16) / W) * 256;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const uint32_t x = v[4 * i + j];
-                fl |= (clamp_i8x4(x, lo, hi) != x ? 1u : 0u) << (4 * i + j);
+                const uint32_t u = v[4 * i + j] ^ 0x80808080u;
+                atomicAdd(&hh[u & 0xFFu], 1u);
+                atomicAdd(&hh[(u >> 8) & 0xFFu], 1u);
+                atomicAdd(&hh[(u >> 16) & 0xFFu], 1u);
+                atomicAdd(&hh[u >> 24], 1u);
                 sched_fence();
             }
         }
-        const int64_t abs0 = d.abs_base + first + wbase;
-        const uint64_t key1 = d.key;
-        auto noise = [&](int owner, int q) -> uint32_t {
-            const int off = (q >> 2) * 1024 + owner * 16 + (q & 3) * 4;
-            const WinParams p = sm.prm[(wbase + off) / W];
-            const Philox4x64 r = philox4x64_10((uint64_t)(abs0 + off) >> 2, seed, key1);
-            uint32_t out = 0;
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int g = c_q8[(uint32_t)(r.w[b] >> 52)];
-                const int q8 = (p.sq8 * g + 32768) >> 16;
-                out |= ((uint32_t)min(max(p.m + q8, -128), 127) & 0xFFu) << (8 * b);
-            }
-            return out;
-        };
-        // Each dword is merged once, so v[q] still holds the input when
-        // its mask is taken.
-        auto mask = [&](int q) -> uint32_t {
-            const WinParams p = sm.prm[(wbase + (q >> 2) * 1024 + lane * 16) / W];
-            const uint32_t x = v[q];
-            return nonzero_byte_mask(clamp_i8x4(x, rep_i16(p.lo * 256), rep_i16(p.hi * 256)) ^ x);
-        };
-        merge_noise(v, fl, sm.noise + wave * 512, noise, mask);
+        wave_sync();
+        const int wl = wave * NWW + lane / G;
+        uint32_t* hw = sm.hist + wl * 256;
+        int mb, D;
+        select_i8<G>(hw, need, mb, D);
+        WinParams p;
+        rfi_window_stats ws;
+        params_i8(hw, mb, D, d.k, W, p, ws);
+        if ((lane & (G - 1)) == 0) sm.prm[wl] = p;
+        ts.s = ws;
+        ts.dst = ((lane & (G - 1)) == 0 && d.stats) ? d.stats + first / W + wl : nullptr;
+        wave_sync();
+        i8_replace<W, NS, MODE>(d, first, seed, sm, v, [&](int i) {
+            return sm.prm[(wbase + i * 1024 + lane * 16) / W];
+        });
     }
 
+    uint8_t* yt = static_cast<uint8_t*>(d.y) + first + wbase + lane * 16;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
         gstore16_nt(yt + i * 1024, make_uint4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]));
+    return ts;
 }
 
 // Mode dispatch: MODES is the set (bit m = mode m) compiled into a kernel.
-template <int W, bool NOISE, int MODES>
-__device__ __forceinline__ void i8_tile_any(const StreamView& d, int64_t first, uint64_t seed,
-                                            I8TileSmem<W, NOISE>& sm)
+template <int W, bool NS, int MODES>
+__device__ __forceinline__ TileStats i8_tile_any(const StreamView& d, int64_t first, uint64_t seed,
+                                                 I8TileSmem<W, NS>& sm, uint32_t (&v)[16])
 {
-    static_assert(!(MODES & 4) || NOISE, "noise needs its LDS scratch");
+    static_assert(!(MODES & 4) || NS, "noise needs its LDS scratch");
     if constexpr (MODES == 1) {
-        i8_tile<W, NOISE, RFI_MODE_ZERO>(d, first, seed, sm);
+        return i8_tile<W, NS, RFI_MODE_ZERO>(d, first, seed, sm, v);
     } else if constexpr (MODES == 2) {
-        i8_tile<W, NOISE, RFI_MODE_CLIP>(d, first, seed, sm);
+        return i8_tile<W, NS, RFI_MODE_CLIP>(d, first, seed, sm, v);
     } else if constexpr (MODES == 4) {
-        i8_tile<W, NOISE, RFI_MODE_NOISE>(d, first, seed, sm);
+        return i8_tile<W, NS, RFI_MODE_NOISE>(d, first, seed, sm, v);
     } else {
-        if ((MODES & 2) && d.mode == RFI_MODE_CLIP) i8_tile<W, NOISE, RFI_MODE_CLIP>(d, first, seed, sm);
-        else if ((MODES & 1) && d.mode == RFI_MODE_ZERO) i8_tile<W, NOISE, RFI_MODE_ZERO>(d, first, seed, sm);
-        else if constexpr ((MODES & 4) != 0) i8_tile<W, NOISE, RFI_MODE_NOISE>(d, first, seed, sm);
+        if ((MODES & 2) && d.mode == RFI_MODE_CLIP) return i8_tile<W, NS, RFI_MODE_CLIP>(d, first, seed, sm, v);
+        if ((MODES & 1) && d.mode == RFI_MODE_ZERO) return i8_tile<W, NS, RFI_MODE_ZERO>(d, first, seed, sm, v);
+        if constexpr ((MODES & 4) != 0) return i8_tile<W, NS, RFI_MODE_NOISE>(d, first, seed, sm, v);
+        TileStats none;
+        none.dst = nullptr;
+        return none;
     }
 }
 
@@ -376,11 +577,13 @@ __device__ __forceinline__ int load_logical(const StreamView& d, int64_t i)
                           : (int)gload(static_cast<const T*>(d.x) + (i - d.head_len));
 }
 
+// Noise sample for absolute index j (one Philox block per 16 samples).
 __device__ __forceinline__ int noise_sample(int64_t j, uint64_t seed, uint32_t key, int m, int sq8,
                                             int vmin, int vmax)
 {
-    const Philox4x64 r = philox4x64_10((uint64_t)j >> 2, seed, key);
-    const int g = c_q8[(uint32_t)(pick4(r, (int)(j & 3)) >> 52)];
+    const Philox4x64 r = philox4x64_10((uint64_t)j >> 4, seed, key);
+    const uint64_t word = pick4(r, (int)((j >> 2) & 3));
+    const int g = c_q8[(uint32_t)(word >> (52 - 12 * (int)(j & 3))) & 0xFFFu];
     const int64_t q = ((int64_t)sq8 * g + 32768) >> 16;
     return (int)min(max((int64_t)m + q, (int64_t)vmin), (int64_t)vmax);
 }
@@ -475,6 +678,34 @@ __device__ __forceinline__ void zero_words(uint32_t* p, int words, int tid, int 
         *reinterpret_cast<uint4*>(p + i) = make_uint4(0, 0, 0, 0);
 }
 
+// 8 int16 noise samples for the chunk whose first absolute index is j0 (a
+// multiple of 8): half (j0 >> 3) & 1 of its 16-sample Philox block; dword
+// k of the result holds samples 2k (low half) and 2k + 1.
+__device__ __forceinline__ uint4 noise_chunk_i16(uint64_t j0, uint64_t seed, uint32_t key, int m,
+                                                 int sq8)
+{
+    const Philox4x64 r = philox4x64_10(j0 >> 4, seed, key);
+    const bool upper = ((j0 >> 3) & 1) != 0;
+    const uint64_t wlo = upper ? r.w[2] : r.w[0];
+    const uint64_t whi = upper ? r.w[3] : r.w[1];
+    uint32_t o[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint64_t word = k < 2 ? wlo : whi;
+        uint32_t nb = 0;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int field = (2 * k + b) & 3;
+            const int g = c_q8[(uint32_t)(word >> (52 - 12 * field)) & 0xFFFu];
+            const int64_t q = ((int64_t)sq8 * g + 32768) >> 16;
+            const int val = (int)min(max((int64_t)m + q, (int64_t)-32768), (int64_t)32767);
+            nb |= ((uint32_t)val & 0xFFFFu) << (16 * b);
+        }
+        o[k] = nb;
+    }
+    return make_uint4(o[0], o[1], o[2], o[3]);
+}
+
 struct I16TileSmem {
     static constexpr int R = 8;
     uint32_t h1[256 * R];  // high digit of x + 32768
@@ -482,7 +713,7 @@ struct I16TileSmem {
     uint32_t h3[256 * R];  // high digit of |x - m|
     uint32_t h4[256];      // low digit of |x - m| inside the MAD bucket
     uint32_t flagged;
-    uint32_t noise[4 * 512];
+    NoiseScratch ns;
 };
 
 __device__ __forceinline__ int lo16(uint32_t v) { return (int)(int16_t)(v & 0xFFFFu); }
@@ -575,38 +806,38 @@ __device__ void i16_tile_8192(const StreamView& d, int64_t first, uint64_t seed,
     const int sq8 = (int)__fmul_rn(sig, 256.0f);
     const int mode = d.mode;
     uint32_t nflag = 0;
-    uint32_t fl = 0;
+    uint32_t cf = 0;  // bit i: slot i holds a flagged sample
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const uint32_t x = v[q];
-        const uint32_t c = pk_clamp_i16(x, lo2, hi2);
-        const uint32_t mk = nonzero_half_mask(c ^ x);
-        nflag += __popc(mk) >> 4;
-        fl |= (mk != 0 ? 1u : 0u) << q;
-        if (mode == RFI_MODE_CLIP) v[q] = c;
-        else if (mode == RFI_MODE_ZERO) v[q] = x & ~mk;
+    for (int i = 0; i < 4; ++i) {
+        uint32_t t = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int q = 4 * i + j;
+            const uint32_t x = v[q];
+            const uint32_t c = pk_clamp_i16(x, lo2, hi2);
+            const uint32_t mk = nonzero_half_mask(c ^ x);
+            nflag += __popc(mk) >> 4;
+            t |= mk;
+            if (mode == RFI_MODE_CLIP) v[q] = c;
+            else if (mode == RFI_MODE_ZERO) v[q] = x & ~mk;
+        }
+        cf |= (t != 0 ? 1u : 0u) << i;
     }
     if (mode == RFI_MODE_NOISE) {
-        const int64_t abs0 = d.abs_base + first + wbase / 2;
-        const uint64_t key1 = d.key;
-        auto noise = [&](int owner, int q) -> uint32_t {
-            const int off = (q >> 2) * 512 + owner * 8 + (q & 3) * 2;  // samples
-            const int64_t j = abs0 + off;
-            const Philox4x64 r = philox4x64_10((uint64_t)j >> 2, seed, key1);
-            uint32_t out = 0;
-#pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                const int g = c_q8[(uint32_t)(pick4(r, (int)((j + b) & 3)) >> 52)];
-                const int64_t q8 = ((int64_t)sq8 * g + 32768) >> 16;
-                const int val = (int)min(max((int64_t)m + q8, (int64_t)-32768), (int64_t)32767);
-                out |= ((uint32_t)val & 0xFFFFu) << (16 * b);
-            }
-            return out;
+        const int64_t abs0 = d.abs_base + first;
+        const uint32_t key1 = d.key;
+        auto merged = [&](int wv, int ln, int slot, uint4 x) -> uint4 {
+            // samples: 2048 per wave, 512 per load slot, 8 per lane
+            const int off = wv * 2048 + slot * 512 + ln * 8;
+            const uint4 nz = noise_chunk_i16((uint64_t)(abs0 + off), seed, key1, m, sq8);
+            const uint32_t m0 = nonzero_half_mask(pk_clamp_i16(x.x, lo2, hi2) ^ x.x);
+            const uint32_t m1 = nonzero_half_mask(pk_clamp_i16(x.y, lo2, hi2) ^ x.y);
+            const uint32_t m2 = nonzero_half_mask(pk_clamp_i16(x.z, lo2, hi2) ^ x.z);
+            const uint32_t m3 = nonzero_half_mask(pk_clamp_i16(x.w, lo2, hi2) ^ x.w);
+            return make_uint4((x.x & ~m0) | (nz.x & m0), (x.y & ~m1) | (nz.y & m1),
+                              (x.z & ~m2) | (nz.z & m2), (x.w & ~m3) | (nz.w & m3));
         };
-        auto mask = [&](int q) -> uint32_t {
-            return nonzero_half_mask(pk_clamp_i16(v[q], lo2, hi2) ^ v[q]);
-        };
-        merge_noise(v, fl, sm.noise + wave * 512, noise, mask);
+        pool_noise(v, cf, sm.ns, merged);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -743,17 +974,44 @@ __device__ __forceinline__ void for_items(const LaunchArgs& a, Body body)
     }
 }
 
-template <int CLS, int MODES, bool PERSIST>
+// One or two tiles per workgroup.  With two, the second tile's loads are
+// issued before the first tile is processed, so they are in flight while
+// the first tile's histogram, selection and replacement run.
+template <int CLS, int MODES, bool PERSIST, int TPW>
 __global__ __launch_bounds__(kBlock) void k_i8_tiles(LaunchArgs a)
 {
     constexpr int W = 512 << CLS;
     constexpr bool NOISE = (MODES & 4) != 0;
     __shared__ I8TileSmem<W, NOISE> sm;
-    for_items<PERSIST>(a, [&](int64_t it) {
-        const Item item = a.items[it];
-        const StreamView d = resolve(a.streams[item.stream], a);
-        i8_tile_any<W, NOISE, MODES>(d, item.first, a.seed, sm);
-    });
+    if constexpr (TPW == 1) {
+        for_items<PERSIST>(a, [&](int64_t it) {
+            const Item item = a.items[it];
+            const StreamView d = resolve(a.streams[item.stream], a);
+            uint32_t v[16];
+            tile_load(d, item.first, v);
+            write_stats(i8_tile_any<W, NOISE, MODES>(d, item.first, a.seed, sm, v));
+        });
+    } else {
+        const int64_t it = 2 * (int64_t)blockIdx.x;
+        if (it >= a.n_items) return;
+        const bool two = it + 1 < a.n_items;
+        const Item ia = a.items[it];
+        const Item ib = a.items[two ? it + 1 : it];
+        const StreamView da = resolve(a.streams[ia.stream], a);
+        const StreamView db = resolve(a.streams[ib.stream], a);
+        uint32_t va[16], vb[16];
+        // Both loads are unconditional (the second repeats the first tile
+        // when there is no second item): a branch around them would make
+        // the first tile's waits cover the second tile's loads too.
+        tile_load(da, ia.first, va);
+        tile_load(db, ib.first, vb);
+        const TileStats sa = i8_tile_any<W, NOISE, MODES>(da, ia.first, a.seed, sm, va);
+        if (two) {
+            if constexpr (W > 4096) __syncthreads();
+            write_stats(i8_tile_any<W, NOISE, MODES>(db, ib.first, a.seed, sm, vb));
+        }
+        write_stats(sa);
+    }
 }
 
 template <bool PERSIST>
@@ -791,13 +1049,15 @@ __global__ __launch_bounds__(kBlock) void k_i8_fused(LaunchArgs a)
         // Items of different classes may follow each other: keep the LDS
         // of the previous item alive until every wave is done with it.
         __syncthreads();
+        uint32_t v[16];
+        tile_load(d, item.first, v);
         switch (i8_tile_class(d.window)) {
-            case 0: i8_tile_any<512, true, 7>(d, item.first, a.seed, sm.c0); break;
-            case 1: i8_tile_any<1024, true, 7>(d, item.first, a.seed, sm.c1); break;
-            case 2: i8_tile_any<2048, true, 7>(d, item.first, a.seed, sm.c2); break;
-            case 3: i8_tile_any<4096, true, 7>(d, item.first, a.seed, sm.c3); break;
-            case 4: i8_tile_any<8192, true, 7>(d, item.first, a.seed, sm.c4); break;
-            default: i8_tile_any<16384, true, 7>(d, item.first, a.seed, sm.c5); break;
+            case 0: write_stats(i8_tile_any<512, true, 7>(d, item.first, a.seed, sm.c0, v)); break;
+            case 1: write_stats(i8_tile_any<1024, true, 7>(d, item.first, a.seed, sm.c1, v)); break;
+            case 2: write_stats(i8_tile_any<2048, true, 7>(d, item.first, a.seed, sm.c2, v)); break;
+            case 3: write_stats(i8_tile_any<4096, true, 7>(d, item.first, a.seed, sm.c3, v)); break;
+            case 4: write_stats(i8_tile_any<8192, true, 7>(d, item.first, a.seed, sm.c4, v)); break;
+            default: write_stats(i8_tile_any<16384, true, 7>(d, item.first, a.seed, sm.c5, v)); break;
         }
     });
 }
@@ -844,53 +1104,80 @@ __global__ __launch_bounds__(kBlock) void k_i16_fused(LaunchArgs a)
 // ---------------------------------------------------------------------------
 // Host launch wrappers.
 // ---------------------------------------------------------------------------
+// wg_per_cu > 0 caps the workgroups resident on one CU by padding each
+// workgroup's LDS allocation (160 KiB per CU), an occupancy limit the
+// autotuner can choose.
+static thread_local int t_wg_per_cu = 0;
+
+void set_wg_per_cu(int n) { t_wg_per_cu = n; }
+
 static hipError_t launch(void (*k)(LaunchArgs), const LaunchArgs& a, int grid, hipStream_t s)
 {
     if (a.n_items <= 0) return hipSuccess;
     if (grid < 1) grid = 1;
+    size_t dyn = 0;
+    if (t_wg_per_cu > 0) {
+        hipFuncAttributes fa;
+        if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(k)) == hipSuccess) {
+            const size_t want = (160u * 1024u) / (size_t)t_wg_per_cu;
+            if (want > fa.sharedSizeBytes) dyn = ((want - fa.sharedSizeBytes) + 255) & ~(size_t)255;
+            if (dyn + fa.sharedSizeBytes > 160u * 1024u) dyn = 0;
+        }
+    }
     LaunchArgs args = a;
     void* kargs[] = {&args};
-    return hipLaunchKernel(reinterpret_cast<const void*>(k), dim3(grid), dim3(kBlock), kargs, 0, s);
+    return hipLaunchKernel(reinterpret_cast<const void*>(k), dim3(grid), dim3(kBlock), kargs, dyn, s);
 }
 
-template <int MODES, bool PERSIST>
-static void (*i8_tile_kernel_m(int cls))(LaunchArgs)
+template <int MODES, bool PERSIST, int T>
+static void (*i8_tile_kernel_t(int cls))(LaunchArgs)
 {
     switch (cls) {
-        case 0: return k_i8_tiles<0, MODES, PERSIST>;
-        case 1: return k_i8_tiles<1, MODES, PERSIST>;
-        case 2: return k_i8_tiles<2, MODES, PERSIST>;
-        case 3: return k_i8_tiles<3, MODES, PERSIST>;
-        case 4: return k_i8_tiles<4, MODES, PERSIST>;
-        case 5: return k_i8_tiles<5, MODES, PERSIST>;
+        case 0: return k_i8_tiles<0, MODES, PERSIST, T>;
+        case 1: return k_i8_tiles<1, MODES, PERSIST, T>;
+        case 2: return k_i8_tiles<2, MODES, PERSIST, T>;
+        case 3: return k_i8_tiles<3, MODES, PERSIST, T>;
+        case 4: return k_i8_tiles<4, MODES, PERSIST, T>;
+        case 5: return k_i8_tiles<5, MODES, PERSIST, T>;
         default: return nullptr;
     }
 }
 
+// Loop-free launches take one or two tiles per workgroup, persistent ones one.
+template <int MODES, bool PERSIST>
+static void (*i8_tile_kernel_m(int cls, int tpw))(LaunchArgs)
+{
+    if constexpr (PERSIST) return i8_tile_kernel_t<MODES, true, 1>(cls);
+    else return tpw == 2 ? i8_tile_kernel_t<MODES, false, 2>(cls) : i8_tile_kernel_t<MODES, false, 1>(cls);
+}
+
 // modes: bit m set if some stream of the launch uses mode m.
 template <bool PERSIST>
-static void (*i8_tile_kernel_p(int cls, int modes))(LaunchArgs)
+static void (*i8_tile_kernel_p(int cls, int modes, int tpw))(LaunchArgs)
 {
     switch (modes) {
-        case 1: return i8_tile_kernel_m<1, PERSIST>(cls);
-        case 2: return i8_tile_kernel_m<2, PERSIST>(cls);
-        case 3: return i8_tile_kernel_m<3, PERSIST>(cls);
-        case 4: return i8_tile_kernel_m<4, PERSIST>(cls);
-        default: return i8_tile_kernel_m<7, PERSIST>(cls);
+        case 1: return i8_tile_kernel_m<1, PERSIST>(cls, tpw);
+        case 2: return i8_tile_kernel_m<2, PERSIST>(cls, tpw);
+        case 3: return i8_tile_kernel_m<3, PERSIST>(cls, tpw);
+        case 4: return i8_tile_kernel_m<4, PERSIST>(cls, tpw);
+        default: return i8_tile_kernel_m<7, PERSIST>(cls, tpw);
     }
 }
 
-static void (*i8_tile_kernel(int cls, int modes, bool persist))(LaunchArgs)
+static void (*i8_tile_kernel(int cls, int modes, bool persist, int tpw))(LaunchArgs)
 {
-    return persist ? i8_tile_kernel_p<true>(cls, modes) : i8_tile_kernel_p<false>(cls, modes);
+    return persist ? i8_tile_kernel_p<true>(cls, modes, 1) : i8_tile_kernel_p<false>(cls, modes, tpw);
 }
 
-hipError_t launch_i8_tiles(int cls, int modes, const LaunchArgs& a, int grid, hipStream_t s)
+hipError_t launch_i8_tiles(int cls, int modes, int tpw, const LaunchArgs& a, int grid, hipStream_t s)
 {
-    // A grid that covers every item runs the loop-free variant.
-    auto k = i8_tile_kernel(cls, modes, grid < a.n_items);
+    // A grid that covers every item runs a loop-free variant with tpw
+    // items per workgroup; a smaller grid runs the persistent variant.
+    const bool persist = grid < a.n_items;
+    if (tpw != 1 && tpw != 2) return hipErrorInvalidValue;
+    auto k = i8_tile_kernel(cls, modes, persist, tpw);
     if (!k) return hipErrorInvalidValue;
-    return launch(k, a, grid, s);
+    return launch(k, a, persist ? grid : (int)((a.n_items + tpw - 1) / tpw), s);
 }
 #define RFI_PICK(K, a, grid) ((grid) < (a).n_items ? K<true> : K<false>)
 hipError_t launch_i8_generic(const LaunchArgs& a, int grid, hipStream_t s)
@@ -922,7 +1209,7 @@ int persistent_grid(int elem_size, int cls, int modes, bool fused)
     if (elem_size == 1) {
         if (fused) k = k_i8_fused<true>;
         else if (cls < 0) k = k_i8_generic<true>;
-        else k = i8_tile_kernel(cls, modes, true);
+        else k = i8_tile_kernel(cls, modes, true, 1);
     } else {
         if (fused) k = k_i16_fused<true>;
         else if (cls < 0) k = k_i16_generic<true>;

@@ -18,13 +18,13 @@ def unpack(specs):
 
 
 def gpu_run(x_cpu, specs, seed, dev, schedule=None, graph=False, inplace=False, stats=True,
-            repeat=1):
+            repeat=1, tpw=None):
     """Run on the device; returns (y numpy, stats structured numpy or None)."""
     L, W, K, M = unpack(specs)
     xd = x_cpu.to(dev)
     fill = SENTINEL if xd.dtype == torch.int8 else 0x5A5A
     yd = xd if inplace else torch.full_like(xd, fill)
-    if schedule is None and not graph:
+    if schedule is None and not graph and tpw is None:
         assert not (inplace and repeat > 1)
         for _ in range(repeat):
             _, st = rfi.mad_filter(xd, L, W, K, M, seed=seed, y=yd, stats=stats)
@@ -32,6 +32,8 @@ def gpu_run(x_cpu, specs, seed, dev, schedule=None, graph=False, inplace=False, 
         plan = rfi.Plan(x_cpu.element_size(), L, W, K, M, seed=seed)
         if schedule is not None:
             plan.set_schedule(schedule)
+        if tpw is not None:
+            plan.set_tiles_per_wg(tpw)
         plan.set_graph(graph)
         st = torch.full((max(plan.n_windows, 1), 4), -7, dtype=torch.int32, device=dev) if stats else None
         stream = torch.cuda.Stream() if graph else None

@@ -32,10 +32,13 @@ def test_plain_one_full_size(gpu):
 
 @pytest.mark.parametrize("W", [512, 1024, 2048, 4096, 8192, 16384])
 @pytest.mark.parametrize("mode", MODES)
-def test_tile_classes(gpu, W, mode):
-    specs = _specs(W, mode, extra=W // 3 + 5)
+@pytest.mark.parametrize("tpw", [1, 2])
+def test_tile_classes(gpu, W, mode, tpw):
+    """Every tile class; one or two tiles per workgroup (odd tile count, so
+    the last two-tile workgroup holds a single tile)."""
+    specs = _specs(W, mode, extra=W // 3 + 5, n=3)  # 3 streams x 3 tiles
     x = synth.gen_packed(specs, seed=W, tag=1)
-    y, st = gpu_run(x, specs, 11, gpu)
+    y, st = gpu_run(x, specs, 11, gpu, tpw=tpw)
     check_against_oracle(x, specs, 11, y, st)
 
 

@@ -302,7 +302,8 @@ def test_int8_discrete_expectations(sigma):
 
 
 def test_noise_statistics():
-    """Noise replacements: Q8 indices uniform, spread ~ sigma_hat."""
+    """Noise replacements: zero mean, spread ~ sigma_hat, and no correlation
+    between neighbouring samples that share a Philox block."""
     g = torch.Generator().manual_seed(12)
     L = 1 << 20
     x = torch.clamp(torch.round(torch.randn(L, generator=g) * 20), -128, 127).to(torch.int8).numpy()
@@ -316,6 +317,13 @@ def test_noise_statistics():
     z = qs / sig
     assert abs(z.mean()) < 0.01
     assert abs(z.std() - 1.0) < 0.02
+    # lag-1 .. lag-15 correlation of q inside 16-sample blocks
+    qf = np.where(flag, q, 0).astype(np.float64)
+    for lag in (1, 3, 4, 15):
+        a, b = qf[:-lag], qf[lag:]
+        both = flag[:-lag] & flag[lag:]
+        c = np.corrcoef(a[both], b[both])[0, 1]
+        assert abs(c) < 0.01, (lag, c)
 
 
 # ---------------------------------------------------------------- noise parts
@@ -359,8 +367,9 @@ def test_noise_value_from_library_parts():
             assert y[i] == v
             continue
         j = a + i
-        bg = np.random.Philox(counter=(j >> 2) - 1, key=np.array([seed, stream], dtype=np.uint64))
-        u = int(bg.random_raw(4)[j & 3]) >> 52
+        bg = np.random.Philox(counter=(j >> 4) - 1, key=np.array([seed, stream], dtype=np.uint64))
+        word = int(bg.random_raw(4)[(j >> 2) & 3])
+        u = (word >> (52 - 12 * (j & 3))) & 0xFFF
         G = round(256 * NormalDist().inv_cdf((u + 0.5) / 4096))
         q = (sq8 * G + 32768) // 65536
         assert y[i] == max(-128, min(127, m + q))
