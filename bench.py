@@ -33,6 +33,27 @@ def algorithmic_bytes(n_samples: int, n_windows: int, elem: int = 1) -> int:
     return 2 * elem * n_samples + 16 * n_windows
 
 
+def measured_traffic(kernel_substr: str):
+    """Calibrated HBM bytes per launch of a kernel from a committed rocprofv3
+    summary under profiles/, if that summary was taken on the current kernel
+    sources; else (None, None)."""
+    import glob
+
+    from paper_1710_08576_amd import profiling
+    cur = profiling.kernel_source_hash()
+    for fn in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        try:
+            summ = profiling.load_summary(fn)
+        except (ValueError, OSError):
+            continue
+        if summ.get("kernel_source_sha256") != cur:
+            continue
+        for name, k in summ.get("kernels", {}).items():
+            if kernel_substr in name:
+                return k["hbm_bytes_per_launch"], os.path.relpath(fn, ROOT)
+    return None, None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +129,10 @@ def main():
     launches = {m: plans[m].info()["launches"] for m in (0, 1, 2)}
     abytes = algorithmic_bytes(n_samples, nw)
     achieved = abytes / (per_mode_ms[dom] * 1e-3) / 1e9
+    # The launch is one tile kernel: class of the window, the mode's bit,
+    # one 16 KiB tile per workgroup.
+    cls = {512: 0, 1024: 1, 2048: 2, 4096: 3, 8192: 4, 16384: 5}[args.window]
+    traffic, traffic_src = measured_traffic("k_i8_tiles<%d, %d, false, 1>" % (cls, 1 << dom))
     modes = {MODE_NAMES[m]: {"ms": round(per_mode_ms[m], 4),
                              "gsamples_s": round(n_samples / per_mode_ms[m] / 1e6, 1),
                              "gb_s": round(abytes / per_mode_ms[m] / 1e6, 1),
@@ -132,8 +157,11 @@ def main():
                    "k": 3.0, "schedule": plans[0].schedule()},
         "modes": modes,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "rfi_i8 window filter, mode %s" % MODE_NAMES[dom],
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                     "calibrated on the copy kernel)",
+                     "traffic_source": traffic_src,
+                     "kernel": "k_i8_tiles<%d, %d, false, 1> (mode %s)" % (cls, 1 << dom, MODE_NAMES[dom]),
                      "algorithmic_bytes_per_launch": abytes},
     }
 
