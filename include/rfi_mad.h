@@ -175,13 +175,23 @@ int rfi_plan_destroy(rfi_plan* plan);
 int rfi_shutdown(void);
 
 /* ------------------------------------------------------------------ */
-/* Serving: blocks of many streams arrive over time; each stream keeps */
-/* its carry (the samples of an unfinished window) and absolute index  */
-/* on the device; blocks are admitted against an HBM budget and filled */
-/* into shared batched launches (continuous batching).                 */
+/* Serving: blocks of many streams arrive over time, as the digitised  */
+/* antenna streams of the paper's real-time backend do (Sec. II-D,     */
+/* Sec. III); each stream keeps its carry (the samples of an           */
+/* unfinished window) on the device and its absolute sample index on   */
+/* the host, so the output equals that of one batch call over the      */
+/* concatenated blocks (same windows, same noise draws).  Blocks are   */
+/* admitted against an HBM budget and an in-flight limit and filled    */
+/* into shared batched launches (continuous batching): stream s runs   */
+/* on lane s % n_lanes (one HIP stream each); a lane launches, per     */
+/* batch, the next admitted block of each of its streams (at most      */
+/* max_batch blocks) as one fused kernel launch plus one carry-update  */
+/* launch, and keeps up to two batches in flight.                      */
 /* Output of a stream is emitted window by window: a submit emits the  */
 /* carry plus as many whole windows as the block completes, into       */
 /* out_dev, which must hold n + W - 1 elements.                        */
+/* Calls on one server are serialised by a mutex.  The server keeps a  */
+/* small record (about 80 bytes) per ticket until it is destroyed.     */
 /* ------------------------------------------------------------------ */
 typedef struct rfi_server rfi_server;
 
@@ -193,7 +203,9 @@ typedef struct {
     uint64_t hbm_budget_bytes;  /* in+out bytes of admitted, unfinished blocks */
     uint64_t seed;              /* Philox key word 0                          */
     int32_t n_lanes;            /* HIP streams used for overlapping batches   */
-    int32_t schedule;           /* rfi_schedule for the batch launches        */
+    int32_t schedule;           /* RFI_SCHED_AUTO or RFI_SCHED_FUSED: one WG  */
+                                /* per work item; RFI_SCHED_FUSED_PERSIST: a  */
+                                /* grid of resident WGs loops over the items */
 } rfi_server_config;
 
 int rfi_server_create(const rfi_server_config* cfg, rfi_server** out);
@@ -231,6 +243,21 @@ int rfi_server_restore(rfi_server* srv, uint32_t stream_id, int64_t next_index,
 /* Counters: admitted, refused (BUSY), completed, launches. */
 int rfi_server_counters(const rfi_server* srv, uint64_t* admitted, uint64_t* refused,
                         uint64_t* completed, uint64_t* launches);
+/* Host steady-clock times (ns) of a ticket's admission and of the moment
+ * the server saw its batch complete (0 while not complete). */
+int rfi_server_ticket_times(rfi_server* srv, uint64_t ticket, int64_t* t_submit_ns,
+                            int64_t* t_done_ns);
+/* Real-time replay: block i of stream stream_ids[i] (device buffers
+ * blocks[i] / outs[i] / stats[i] as for submit, lengths[i] samples)
+ * arrives arrival_ns[i] after the call starts (non-decreasing).  The call
+ * admits each block at its arrival time (later, in arrival order, while
+ * the server answers BUSY), dispatches, and returns when all are done;
+ * latency_ns[i] = completion time - arrival time, samples_emitted[i] (may
+ * be NULL) as for poll.  stats may be NULL (no statistics). */
+int rfi_server_replay(rfi_server* srv, int64_t n_blocks, const uint32_t* stream_ids,
+                      const int64_t* arrival_ns, const void* const* blocks, void* const* outs,
+                      const int64_t* lengths, rfi_window_stats* const* stats,
+                      int64_t* latency_ns, int64_t* samples_emitted);
 int rfi_server_destroy(rfi_server* srv);
 
 #ifdef __cplusplus

@@ -75,6 +75,8 @@ _SIGS = {
     "rfi_server_snapshot": (ctypes.c_int, [P, U32, P, P, P]),
     "rfi_server_restore": (ctypes.c_int, [P, U32, I64, I32, P]),
     "rfi_server_counters": (ctypes.c_int, [P, P, P, P, P]),
+    "rfi_server_ticket_times": (ctypes.c_int, [P, U64, P, P]),
+    "rfi_server_replay": (ctypes.c_int, [P, I64, P, P, P, P, P, P, P, P]),
     "rfi_server_destroy": (ctypes.c_int, [P]),
     "rfi_ubench_copy": (ctypes.c_int, [P, P, U64, I32, P]),
 }
@@ -243,6 +245,131 @@ class Plan:
     def close(self):
         if getattr(self, "h", None):
             load().rfi_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Serving runtime: per-stream device carry, admission, batched launches.
+
+    Buffers are CUDA tensors owned by the caller; a block's input, output
+    and stats tensors must stay alive until its ticket completes."""
+
+    def __init__(self, elem_size=1, max_streams=64, max_inflight=256, max_batch=64,
+                 hbm_budget_bytes=1 << 34, seed=0, n_lanes=2, schedule="fused"):
+        if isinstance(schedule, str):
+            schedule = SCHEDULES[schedule]
+        self.cfg = ServerConfig(elem_size, max_streams, max_inflight, max_batch,
+                                hbm_budget_bytes, seed, n_lanes, schedule)
+        self.elem_size = elem_size
+        self.windows = {}
+        h = ctypes.c_void_p()
+        _check(load().rfi_server_create(ctypes.byref(self.cfg), ctypes.byref(h)),
+               "rfi_server_create")
+        self.h = h
+
+    def add_stream(self, sid, window, k, mode):
+        _check(load().rfi_server_add_stream(self.h, sid, window, k, mode), "rfi_server_add_stream")
+        self.windows[sid] = window
+
+    def out_elems(self, sid, n):
+        """Output elements a block of n samples of stream sid needs."""
+        return n + self.windows[sid] - 1
+
+    def stats_entries(self, sid, n):
+        w = self.windows[sid]
+        return (n + w - 1 + w - 1) // w
+
+    def submit(self, sid, block, out, stats=None, n=None) -> int:
+        """Returns the ticket; raises RfiError (status RFI_ERR_BUSY) on refusal."""
+        if n is None:
+            n = block.numel()
+        t = ctypes.c_uint64()
+        _check(load().rfi_server_submit(self.h, sid, _tptr(block), _tptr(out), n, _tptr(stats),
+                                        ctypes.byref(t)), "rfi_server_submit")
+        return t.value
+
+    def try_submit(self, sid, block, out, stats=None, n=None):
+        """Like submit, but returns None when admission is refused."""
+        try:
+            return self.submit(sid, block, out, stats, n)
+        except RfiError as e:
+            if e.status == -6:
+                return None
+            raise
+
+    def dispatch(self):
+        _check(load().rfi_server_dispatch(self.h), "rfi_server_dispatch")
+
+    def poll(self, ticket):
+        """(done, samples_emitted, windows_emitted)."""
+        d = ctypes.c_int32()
+        se, we = ctypes.c_int64(), ctypes.c_int64()
+        _check(load().rfi_server_poll(self.h, ticket, ctypes.byref(d), ctypes.byref(se),
+                                      ctypes.byref(we)), "rfi_server_poll")
+        return bool(d.value), se.value, we.value
+
+    def sync(self):
+        _check(load().rfi_server_sync(self.h), "rfi_server_sync")
+
+    def flush(self, sid, out, stats=None) -> int:
+        n = ctypes.c_int64()
+        _check(load().rfi_server_flush(self.h, sid, _tptr(out), _tptr(stats), ctypes.byref(n)),
+               "rfi_server_flush")
+        return n.value
+
+    def snapshot(self, sid):
+        """(next_index, carry samples as a numpy array)."""
+        dt = np.int8 if self.elem_size == 1 else np.int16
+        buf = np.zeros(max(self.windows[sid], 1), dtype=dt)
+        ni, cl = ctypes.c_int64(), ctypes.c_int32()
+        _check(load().rfi_server_snapshot(self.h, sid, ctypes.byref(ni), ctypes.byref(cl),
+                                          _ptr(buf)), "rfi_server_snapshot")
+        return ni.value, buf[:cl.value].copy()
+
+    def restore(self, sid, next_index, carry):
+        dt = np.int8 if self.elem_size == 1 else np.int16
+        c = np.ascontiguousarray(carry, dtype=dt)
+        _check(load().rfi_server_restore(self.h, sid, next_index, len(c),
+                                         _ptr(c) if len(c) else None), "rfi_server_restore")
+
+    def counters(self):
+        v = [ctypes.c_uint64() for _ in range(4)]
+        _check(load().rfi_server_counters(self.h, *[ctypes.byref(x) for x in v]),
+               "rfi_server_counters")
+        return dict(zip(("admitted", "refused", "completed", "launches"), (x.value for x in v)))
+
+    def ticket_times(self, ticket):
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(load().rfi_server_ticket_times(self.h, ticket, ctypes.byref(a), ctypes.byref(b)),
+               "rfi_server_ticket_times")
+        return a.value, b.value
+
+    def replay(self, stream_ids, arrival_ns, blocks, outs, stats=None):
+        """Real-time replay (see rfi_server_replay); returns (latency_ns,
+        samples_emitted) numpy arrays."""
+        n = len(stream_ids)
+        sid = np.ascontiguousarray(stream_ids, dtype=np.uint32)
+        arr = np.ascontiguousarray(arrival_ns, dtype=np.int64)
+        bp = np.array([b.data_ptr() for b in blocks], dtype=np.uint64)
+        op = np.array([o.data_ptr() for o in outs], dtype=np.uint64)
+        ln = np.array([b.numel() for b in blocks], dtype=np.int64)
+        sp = np.array([s.data_ptr() for s in stats], dtype=np.uint64) if stats is not None else None
+        lat = np.zeros(n, np.int64)
+        em = np.zeros(n, np.int64)
+        _check(load().rfi_server_replay(self.h, n, _ptr(sid), _ptr(arr), _ptr(bp), _ptr(op),
+                                        _ptr(ln), _ptr(sp) if sp is not None else None,
+                                        _ptr(lat), _ptr(em)), "rfi_server_replay")
+        return lat, em
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().rfi_server_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -123,6 +123,20 @@ hipError_t launch_i16_tiles(int cls, const LaunchArgs& a, int grid, hipStream_t 
 hipError_t launch_i16_generic(const LaunchArgs& a, int grid, hipStream_t s);
 hipError_t launch_i16_fused(const LaunchArgs& a, int grid, hipStream_t s);
 
+// Serving carry update: copies logical elements [from, from + count) of the
+// concatenation (head[0 .. head_len), body[...]) to dst.  Addresses are
+// absolute device addresses.
+struct CarryItem {
+    uint64_t head;
+    uint64_t body;
+    uint64_t dst;
+    int32_t head_len;
+    int32_t from;
+    int32_t count;
+    int32_t elem;  // 1 or 2 bytes
+};
+hipError_t launch_carry(const CarryItem* items, int n_items, hipStream_t s);
+
 // Occupancy cap for the launches issued by this thread (0: none).
 void set_wg_per_cu(int n);
 

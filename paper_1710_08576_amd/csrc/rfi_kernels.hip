@@ -1101,6 +1101,21 @@ __global__ __launch_bounds__(kBlock) void k_i16_fused(LaunchArgs a)
     });
 }
 
+__global__ __launch_bounds__(kBlock) void k_carry(const CarryItem* __restrict__ items)
+{
+    const CarryItem c = items[blockIdx.x];
+    for (int i = (int)threadIdx.x; i < c.count; i += kBlock) {
+        const int j = c.from + i;
+        const uint64_t src = j < c.head_len ? c.head + (uint64_t)j * c.elem
+                                            : c.body + (uint64_t)(j - c.head_len) * c.elem;
+        const uint64_t dst = c.dst + (uint64_t)i * c.elem;
+        if (c.elem == 1)
+            gstore(reinterpret_cast<uint8_t*>(dst), gload(reinterpret_cast<const uint8_t*>(src)));
+        else
+            gstore(reinterpret_cast<uint16_t*>(dst), gload(reinterpret_cast<const uint16_t*>(src)));
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Host launch wrappers.
 // ---------------------------------------------------------------------------
@@ -1202,6 +1217,13 @@ hipError_t launch_i16_fused(const LaunchArgs& a, int grid, hipStream_t s)
     return launch(RFI_PICK(k_i16_fused, a, grid), a, grid, s);
 }
 #undef RFI_PICK
+
+hipError_t launch_carry(const CarryItem* items, int n_items, hipStream_t s)
+{
+    if (n_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_carry, dim3(n_items), dim3(kBlock), 0, s, items);
+    return hipGetLastError();
+}
 
 int persistent_grid(int elem_size, int cls, int modes, bool fused)
 {
