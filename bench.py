@@ -8,8 +8,20 @@ launch over the full batch), so value = 3 * 60 * 2^24 samples / step time.
 Inputs are drawn on the device before timing and stay resident in HBM.
 
 Prints one JSON line.  Extra keys: per-mode rates, the W = 16384 variant,
-the roofline of the dominant kernel (HIP events on the launch stream) and
-the CPU oracle timed on a bounded sample of the same workload.
+the roofline of the dominant kernel (HIP events on the launch stream), the
+CPU oracle timed on a bounded sample of the same workload, and the other
+workloads of the method:
+
+* batching: 64 uneven int8 streams (L U[2^18, 2^24], W from 512..16384,
+  k U[2.5, 5], mixed modes) as one plain launch per stream versus one
+  batched launch (persistent, fused, graph-replayed; and the autotuned pick);
+* int16: 60 x 2^23 int16 samples, window 8192, noise replacement;
+* serving: 60 int8 streams, 2^20-sample blocks arriving as Poisson processes
+  at the 800 Msample/s real-time rate (mean gap = deadline = 1.31072 ms),
+  replayed in real time through the serving runtime; p50/p99 latency from
+  arrival to completion against the deadline, plus a run with a block size
+  that is no multiple of any window (carry-over) and a saturated run with
+  every block ready at once (serving throughput).
 """
 from __future__ import annotations
 
@@ -64,6 +76,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the W=16384 variant")
+    ap.add_argument("--no-batching", action="store_true")
+    ap.add_argument("--no-int16", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-blocks", type=int, default=10000,
+                    help="blocks per stream in the real-time serving replay")
     ap.add_argument("--with-copy", action="store_true",
                     help="after timing, run the HBM copy microbenchmark on the same buffers "
                          "(a kernel of known traffic, to calibrate hardware byte counters)")
@@ -185,6 +202,16 @@ def main():
         for p in plans16.values():
             p.close()
 
+    if not args.no_batching:
+        out["batching"] = bench_batching(args, dev)
+    if not args.no_int16:
+        out["int16"] = bench_int16(args, dev)
+    if not args.no_serving:
+        del x, y
+        torch.cuda.empty_cache()
+        out["serving"] = bench_serving(args, dev)
+        x = synth.gen_packed(specs, seed=0, tag=1000, device=dev)
+
     # CPU oracle on a bounded sample: whole streams, cycling the modes.
     if not args.no_cpu_baseline:
         import oracle
@@ -204,6 +231,174 @@ def main():
                                "sample": "%d of the %d streams (2^24 int8 each, window %d, k 3), "
                                          "modes zero/clip/noise in turn" % (s, N_STREAMS, args.window)}
     print(json.dumps(out))
+
+
+def _time_events(fn, iters, stream):
+    """Mean ms of fn() over iters runs, HIP events on `stream`."""
+    import numpy as np
+    import torch
+    evs = []
+    for _ in range(iters):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        evs.append((a, b))
+    torch.cuda.synchronize()
+    return float(np.mean([a.elapsed_time(b) for a, b in evs]))
+
+
+def bench_batching(args, dev):
+    """One launch per stream versus the batched launch, same buffers."""
+    import torch
+
+    import paper_1710_08576_amd as rfi
+    from paper_1710_08576_amd import synth
+    specs = synth.batching()
+    L = [s.length for s in specs]
+    W = [s.window for s in specs]
+    K = [s.k for s in specs]
+    M = [s.mode for s in specs]
+    x = synth.gen_packed(specs, seed=0, tag=2000, device=dev)
+    y = torch.empty_like(x)
+    nw = rfi.layout(L, W)[2]
+    st = torch.empty((nw, 4), dtype=torch.int32, device=dev)
+    n = sum(L)
+    abytes = algorithmic_bytes(n, nw)
+    stream = torch.cuda.Stream()
+    iters = max(10, args.steps // 2)
+    res = {"workload": "64 int8 streams, L U[2^18,2^24] (%d samples), W 512..16384, "
+                       "k U[2.5,5], mixed modes" % n}
+    variants = [("per_stream_launches", "per_stream", False), ("batched_fused_persist_graph",
+                                                               "fused_persist", True),
+                ("batched_split_graph", "split", True)]
+    with torch.cuda.stream(stream):
+        for name, sched, graph in variants:
+            p = rfi.Plan(1, L, W, K, M, seed=3)
+            p.set_schedule(sched)
+            p.set_graph(graph)
+            for _ in range(3):
+                p.execute(x, y, st, stream=stream)
+            ms = _time_events(lambda: p.execute(x, y, st, stream=stream), iters, stream)
+            res[name] = {"ms": round(ms, 4), "gsamples_s": round(n / ms / 1e6, 1),
+                         "gb_s": round(abytes / ms / 1e6, 1), "launches": p.info()["launches"]}
+            p.close()
+        p = rfi.Plan(1, L, W, K, M, seed=3)
+        best, best_ms = p.autotune(x, y, st, iters=5, stream=stream)
+        p.set_graph(True)
+        for _ in range(3):
+            p.execute(x, y, st, stream=stream)
+        ms = _time_events(lambda: p.execute(x, y, st, stream=stream), iters, stream)
+        inv = {v: k for k, v in rfi.SCHEDULES.items()}
+        res["batched_autotuned_graph"] = {"ms": round(ms, 4), "gsamples_s": round(n / ms / 1e6, 1),
+                                          "gb_s": round(abytes / ms / 1e6, 1),
+                                          "schedule": inv.get(best, best),
+                                          "launches": p.info()["launches"]}
+        p.close()
+    base = res["per_stream_launches"]["ms"]
+    res["speedup_batched_vs_per_stream"] = round(base / res["batched_autotuned_graph"]["ms"], 3)
+    res["roofline_frac_batched"] = round(res["batched_autotuned_graph"]["gb_s"] / HBM_PEAK_GBS, 4)
+    return res
+
+
+def bench_int16(args, dev):
+    import torch
+
+    import paper_1710_08576_amd as rfi
+    from paper_1710_08576_amd import synth
+    specs = synth.int16_path()
+    L = [s.length for s in specs]
+    x = synth.gen_packed(specs, seed=0, tag=3000, device=dev)
+    y = torch.empty_like(x)
+    nw = rfi.layout(L, [8192] * len(L))[2]
+    st = torch.empty((nw, 4), dtype=torch.int32, device=dev)
+    p = rfi.Plan(2, L, [8192] * len(L), [3.0] * len(L), [2] * len(L), seed=5)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        p.execute(x, y, st, stream=stream)
+    ms = _time_events(lambda: p.execute(x, y, st, stream=stream), max(10, args.steps // 2), stream)
+    n = sum(L)
+    ab = algorithmic_bytes(n, nw, elem=2)
+    p.close()
+    return {"workload": "60 x 2^23 int16, window 8192, k 3, noise", "ms": round(ms, 4),
+            "gsamples_s": round(n / ms / 1e6, 1), "gb_s": round(ab / ms / 1e6, 1),
+            "roofline_frac": round(ab / ms / 1e6 / HBM_PEAK_GBS, 4)}
+
+
+DEADLINE_NS = (1 << 20) / 800e6 * 1e9  # one 2^20-sample block at 800 Msample/s
+
+
+def bench_serving(args, dev):
+    """Real-time replay through the serving runtime (see module docstring)."""
+    import numpy as np
+    import torch
+
+    import paper_1710_08576_amd as rfi
+    from paper_1710_08576_amd import synth
+    specs = synth.serving_streams()
+    ns = len(specs)
+    ring = 64
+    block = 1 << 20
+    # ring of pre-generated blocks per stream, resident on the device
+    xs = []
+    for i, s in enumerate(specs):
+        s.length = ring * block
+        xs.append(synth.gen_stream(s, 0, 4000, i, device=dev))
+    maxw = max(s.window for s in specs)
+    outs = torch.empty((ns, ring, block + maxw), dtype=torch.int8, device=dev)
+    stats = torch.empty((ns, ring, (block + 2 * maxw) // 512, 4), dtype=torch.int32, device=dev)
+    res = {"workload": "60 int8 streams, 2^20-sample blocks, Poisson arrivals at 800 Msample/s "
+                       "per stream (mean gap %.5f ms), W %s, k 3, clip" %
+                       (DEADLINE_NS / 1e6, sorted({s.window for s in specs})),
+           "deadline_ms": DEADLINE_NS / 1e6}
+
+    def run(n_per_stream, blen, arrivals):
+        srv = rfi.Server(elem_size=1, max_streams=ns, max_inflight=1024, max_batch=64,
+                         hbm_budget_bytes=2 << 30, seed=7, n_lanes=4, schedule="fused")
+        for i, s in enumerate(specs):
+            srv.add_stream(i, s.window, s.k, s.mode)
+        sid = np.repeat(np.arange(ns, dtype=np.uint32)[None, :], n_per_stream, 0)
+        blk = np.repeat(np.arange(n_per_stream)[:, None], ns, 1)
+        t = arrivals(n_per_stream)
+        order = np.argsort(t.ravel(), kind="stable")
+        sid, blk, t = sid.ravel()[order], blk.ravel()[order], t.ravel()[order]
+        slot = blk % ring
+        # blocks of length blen tile the ring's stream buffer (wrapping)
+        start = (blk % ((ring * block) // blen)) * blen
+        bptr = np.array([xs[i].data_ptr() for i in range(ns)], np.uint64)[sid] + start.astype(np.uint64)
+        optr = (np.uint64(outs.data_ptr()) + ((sid.astype(np.uint64) * ring + slot.astype(np.uint64))
+                                              * np.uint64(outs.shape[2])))
+        sptr = (np.uint64(stats.data_ptr()) + ((sid.astype(np.uint64) * ring + slot.astype(np.uint64))
+                                               * np.uint64(stats.shape[2] * 16)))
+        # 16-byte alignment of the block addresses
+        assert np.all(bptr % 16 == 0) and np.all(optr % 16 == 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat, em = srv.replay_ptrs(sid, t, bptr, optr, np.full(len(sid), blen), sptr)
+        wall = time.perf_counter() - t0
+        c = srv.counters()
+        srv.close()
+        lat_ms = lat / 1e6
+        n_blocks = len(sid)
+        r = {"blocks": int(n_blocks), "block_samples": blen,
+             "p50_ms": round(float(np.percentile(lat_ms, 50)), 4),
+             "p99_ms": round(float(np.percentile(lat_ms, 99)), 4),
+             "p999_ms": round(float(np.percentile(lat_ms, 99.9)), 4),
+             "max_ms": round(float(lat_ms.max()), 4),
+             "deadline_misses": int((lat > DEADLINE_NS).sum()),
+             "gsamples_s": round(n_blocks * blen / wall / 1e9, 2),
+             "launches": c["launches"], "refused": c["refused"]}
+        return r
+
+    def poisson(n):
+        rng = np.random.default_rng(11)
+        gaps = rng.exponential(DEADLINE_NS, size=(n, ns))
+        return np.cumsum(gaps, 0).astype(np.int64)
+
+    res["realtime"] = run(args.serve_blocks, block, poisson)
+    res["realtime_carry"] = run(max(200, args.serve_blocks // 5), 1_000_000, poisson)
+    res["saturated"] = run(200, block, lambda n: np.zeros((n, ns), np.int64))
+    return res
 
 
 if __name__ == "__main__":

@@ -367,6 +367,22 @@ class Server:
                                         _ptr(lat), _ptr(em)), "rfi_server_replay")
         return lat, em
 
+    def replay_ptrs(self, stream_ids, arrival_ns, block_ptrs, out_ptrs, lengths, stats_ptrs=None):
+        """replay() on raw device addresses (numpy uint64 arrays)."""
+        n = len(stream_ids)
+        sid = np.ascontiguousarray(stream_ids, dtype=np.uint32)
+        arr = np.ascontiguousarray(arrival_ns, dtype=np.int64)
+        bp = np.ascontiguousarray(block_ptrs, dtype=np.uint64)
+        op = np.ascontiguousarray(out_ptrs, dtype=np.uint64)
+        ln = np.ascontiguousarray(lengths, dtype=np.int64)
+        sp = np.ascontiguousarray(stats_ptrs, dtype=np.uint64) if stats_ptrs is not None else None
+        lat = np.zeros(n, np.int64)
+        em = np.zeros(n, np.int64)
+        _check(load().rfi_server_replay(self.h, n, _ptr(sid), _ptr(arr), _ptr(bp), _ptr(op),
+                                        _ptr(ln), _ptr(sp) if sp is not None else None,
+                                        _ptr(lat), _ptr(em)), "rfi_server_replay")
+        return lat, em
+
     def close(self):
         if getattr(self, "h", None):
             load().rfi_server_destroy(self.h)

@@ -58,6 +58,28 @@ __device__ __forceinline__ float threshold_of(int D, float k, float& sig)
 // inclusive cumulative counts and every lane of the group has mb (median
 // + 128) and D.  Used when a wave holds several windows.
 // ---------------------------------------------------------------------------
+// Smallest d in [0, 256) with f(d) >= need, for f non-decreasing with
+// f(255) >= need, i.e. the number of d with f(d) < need.  The G lanes of a
+// group test G evenly spaced candidates per step (a G-ary search), so the
+// answer takes log_G(256) steps instead of a test of every d.
+template <int G, int SPAN, class F>
+__device__ __forceinline__ int group_search(int lo, uint32_t need, const F& f)
+{
+    if constexpr (SPAN <= 1) {
+        return lo;
+    } else {
+        constexpr int STEP = SPAN >= G ? SPAN / G : 1;
+        constexpr int NC = SPAN >= G ? G : SPAN;  // candidates tested
+        const int sl = lane_id() & (G - 1);
+        const int d = min(lo + (sl + 1) * STEP - 1, 255);
+        const bool below = (NC == G || sl < NC) && f(d) < need;
+        return group_search<G, STEP>(lo + group_count<G>(below) * STEP, need, f);
+    }
+}
+
+// Median bin and MAD of one window from its 256-bin histogram hw (bin v
+// counts samples x = v - 128), by the G lanes of a group.  Leaves the
+// cumulative counts C[v] = #{x <= v - 128} in hw.
 template <int G>
 __device__ __forceinline__ void select_i8(uint32_t* hw, uint32_t need, int& mb, int& D)
 {
@@ -82,25 +104,16 @@ __device__ __forceinline__ void select_i8(uint32_t* hw, uint32_t need, int& mb, 
 #pragma unroll
     for (int j = 0; j < BPL; j += 4)
         *reinterpret_cast<uint4*>(my + j) = make_uint4(c[j], c[j + 1], c[j + 2], c[j + 3]);
-    // C is non-decreasing in the bin, and bins run in lane order, so the
-    // median bin is the number of bins with C < need.
-    int below = 0;
-#pragma unroll
-    for (int j = 0; j < BPL; ++j) below += group_count<G>(c[j] < need);
-    mb = below;
     wave_sync();
+    // The median bin is the first v with C[v] >= need.
+    mb = group_search<G, 256>(0, need, [&](int v) { return hw[v]; });
     // #{|x - m| <= d} = C[min(mb + d, 255)] - C[mb - d - 1] is non-decreasing
-    // in d, so D is the number of d with a count below `need`.
-    int dbelow = 0;
-#pragma unroll
-    for (int j = 0; j < BPL; ++j) {
-        const int d = sl * BPL + j;
-        const int up = min(mb + d, 255);
-        const int dn = mb - d - 1;
-        const uint32_t lowc = dn >= 0 ? hw[max(dn, 0)] : 0u;
-        dbelow += group_count<G>(hw[up] - lowc < need);
-    }
-    D = dbelow;
+    // in d and reaches the window size at d = 255; D is its first d >= need.
+    const int m0 = mb;
+    D = group_search<G, 256>(0, need, [&](int d) {
+        const int dn = m0 - d - 1;
+        return hw[min(m0 + d, 255)] - (dn >= 0 ? hw[max(dn, 0)] : 0u);
+    });
 }
 
 // Window parameters and statistics from the cumulative histogram hw.
@@ -321,6 +334,10 @@ __device__ __forceinline__ void pool_noise(uint32_t (&v)[16], uint32_t cf, Noise
 // ---------------------------------------------------------------------------
 // int8 tiles: 16 KiB of whole windows of one class W, 64 bytes per lane.
 // ---------------------------------------------------------------------------
+// Narrow windows: one 256-bin histogram per window, 8 words apart in bank
+// order, so the same bin of the windows of a wave falls in different banks.
+constexpr int kNarrowStride = 264;
+
 template <int W, bool NS>
 struct I8TileSmem {
     static constexpr int kWin = 16384 / W;
@@ -328,7 +345,7 @@ struct I8TileSmem {
     static constexpr int kWPW = kWide ? W / 4096 : 1;  // waves per window
     // wide: per-wave replicated histograms; W = 4096 keeps its cumulative
     // counts in replica 0 of its wave, larger W in pc.
-    uint32_t hist[kWide ? 4 * kWaveHistWords : kWin * 256];
+    uint32_t hist[kWide ? 4 * kWaveHistWords : kWin * kNarrowStride];
     uint32_t tot[kWPW > 1 ? kWin * 256 : 0];
     uint32_t pc[kWPW > 1 ? kWin * kPadC : 0];
     WinParams prm[kWin];
@@ -496,13 +513,14 @@ __device__ __forceinline__ TileStats i8_tile(const StreamView& d, int64_t first,
         // Several windows per wave: one 256-bin histogram of x + 128 per window.
         constexpr int NWW = 4096 / W;  // windows per wave
         constexpr int G = 64 / NWW;    // lanes per window in the scan
-        uint4* h0 = reinterpret_cast<uint4*>(sm.hist + wave * NWW * 256);
+        uint32_t* h0 = sm.hist + wave * NWW * kNarrowStride;
 #pragma unroll
-        for (int j = 0; j < NWW; ++j) h0[j * 64 + lane] = make_uint4(0, 0, 0, 0);
+        for (int j = 0; j < NWW; ++j)
+            reinterpret_cast<uint4*>(h0 + j * kNarrowStride)[lane] = make_uint4(0, 0, 0, 0);
         wave_sync();
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            uint32_t* hh = sm.hist + ((wbase + i * 1024 + lane * 16) / W) * 256;
+            uint32_t* hh = sm.hist + ((wbase + i * 1024 + lane * 16) / W) * kNarrowStride;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const uint32_t u = v[4 * i + j] ^ 0x80808080u;
@@ -515,7 +533,7 @@ __device__ __forceinline__ TileStats i8_tile(const StreamView& d, int64_t first,
         }
         wave_sync();
         const int wl = wave * NWW + lane / G;
-        uint32_t* hw = sm.hist + wl * 256;
+        uint32_t* hw = sm.hist + wl * kNarrowStride;
         int mb, D;
         select_i8<G>(hw, need, mb, D);
         WinParams p;

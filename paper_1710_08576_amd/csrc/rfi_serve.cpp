@@ -7,10 +7,13 @@
 // stream had been one batch (same windows, same noise keys).
 //
 // Each stream is bound to one "lane" (a HIP stream).  A lane dispatches
-// batches: every admitted block of its streams that is next in its stream's
-// order, at most one per stream per batch, up to max_batch blocks, as one
-// fused kernel launch over a work table plus one carry-update launch.  The
-// carry chain of a stream therefore follows HIP stream order.  A lane keeps
+// batches: admitted blocks of its streams, taken round-robin in each
+// stream's order, up to max_batch blocks, as one fused kernel launch over a
+// work table plus one carry-update launch.  Within a batch, the head window
+// of a stream's next block reads its carry straight from the previous
+// block's buffer; the carry left at the end of the batch is copied to the
+// stream's device carry buffer by the carry-update launch, so the carry
+// chain across batches follows HIP stream order.  A lane keeps
 // up to kSlotsPerLane batches in flight; blocks that arrive meanwhile wait
 // for the next batch of their lane (continuous batching), so the work of
 // different lanes, and of queued batches, overlaps on the device.  Blocks
@@ -80,12 +83,33 @@ struct Slot {
 
 size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 
+// Where the carry of a stream lies while a batch is being built: in the
+// stream's device carry buffer (at batch start) or at the end of a block
+// already in the batch.  `open` turns false once a block leaves a carry
+// that spans the old carry and that whole block; that carry goes through
+// the carry-update launch, so later blocks of the stream wait for the next
+// batch.
+struct Chain {
+    uint64_t src = 0;
+    int32_t len = 0;
+    bool in_buffer = true;
+    bool open = true;
+};
+
+constexpr size_t kSlotPrealloc = 1 << 20;  // table bytes per slot at creation
+
 struct Lane {
     hipStream_t s = nullptr;
     Slot slots[kSlotsPerLane];
     std::deque<int> inflight;  // slot indices in launch order
     int rr = 0;                // round-robin start among the lane's streams
     std::vector<uint32_t> members;
+    // Work tables of the batch being built (kept to reuse their storage).
+    std::vector<StreamDesc> descs;
+    std::vector<Item> items;
+    std::vector<CarryItem> carries;
+    std::vector<uint64_t> batch;
+    std::vector<Chain> chains;
 };
 
 }  // namespace
@@ -94,7 +118,7 @@ struct rfi_server {
     rfi_server_config cfg;
     int device = 0;
     std::vector<SrvStream> streams;
-    std::vector<TicketRec> tickets;  // index = ticket id - 1
+    std::deque<TicketRec> tickets;  // index = ticket id - 1 (never relocated)
     std::vector<Lane> lanes;
     uint64_t bytes_inflight = 0;
     int64_t inflight = 0;
@@ -157,9 +181,7 @@ int upload(Slot& sl, const std::vector<StreamDesc>& descs, const std::vector<Ite
 
 // Work of one block appended to the batch tables (host side); updates the
 // stream's carry bookkeeping.
-void plan_block(rfi_server* srv, SrvStream& st, uint32_t sid, TicketRec& t,
-                std::vector<StreamDesc>& descs, std::vector<Item>& items,
-                std::vector<CarryItem>& carries)
+void plan_block(rfi_server* srv, SrvStream& st, uint32_t sid, TicketRec& t, Chain& ch, Lane& L)
 {
     const int elem = srv->cfg.elem_size;
     const int64_t c = st.carry_len, n = t.n, W = st.W;
@@ -182,14 +204,14 @@ void plan_block(rfi_server* srv, SrvStream& st, uint32_t sid, TicketRec& t,
         if (h) {
             StreamDesc d = base_desc();
             d.x_off = (uint64_t)(uintptr_t)t.block;
-            d.head_off = (uint64_t)(uintptr_t)st.carry[st.cur];
+            d.head_off = ch.src;
             d.head_len = (int32_t)c;
             d.length = W;
             d.y_off = (uint64_t)(uintptr_t)t.out;
             d.stats_off = (uint64_t)(uintptr_t)t.stats;
             d.abs_base = st.next_abs;
-            items.push_back(Item{(int32_t)descs.size(), kItemGeneric, 0});
-            descs.push_back(d);
+            L.items.push_back(Item{(int32_t)L.descs.size(), kItemGeneric, 0});
+            L.descs.push_back(d);
         }
         const int64_t nb = nw - h;
         if (nb > 0) {
@@ -201,8 +223,8 @@ void plan_block(rfi_server* srv, SrvStream& st, uint32_t sid, TicketRec& t,
             d.stats_off = (uint64_t)(uintptr_t)(t.stats ? t.stats + h : nullptr);
             d.length = nb * W;
             d.abs_base = st.next_abs + h * W;
-            const int ds = (int32_t)descs.size();
-            descs.push_back(d);
+            const int ds = (int32_t)L.descs.size();
+            L.descs.push_back(d);
             const int cls = elem == 1 ? i8_tile_class(st.W) : i16_tile_class(st.W);
             const int64_t tile_samples = kTileBytes / elem;
             int64_t first_generic = 0;
@@ -210,28 +232,61 @@ void plan_block(rfi_server* srv, SrvStream& st, uint32_t sid, TicketRec& t,
             // start a 16-sample block of the stream's index space.
             if (cls >= 0 && (x % 16) == 0 && (y % 16) == 0 && (d.abs_base % 16) == 0) {
                 const int64_t nt = (nb * W) / tile_samples;
-                for (int64_t i = 0; i < nt; ++i) items.push_back(Item{ds, kItemTile, i * tile_samples});
+                for (int64_t i = 0; i < nt; ++i) L.items.push_back(Item{ds, kItemTile, i * tile_samples});
                 first_generic = nt * (tile_samples / W);
             }
-            for (int64_t w = first_generic; w < nb; ++w) items.push_back(Item{ds, kItemGeneric, w});
+            for (int64_t w = first_generic; w < nb; ++w) L.items.push_back(Item{ds, kItemGeneric, w});
         }
     }
-    if (newc > 0) {
+    if (newc > 0 && nw == 0 && c > 0) {
+        // The new carry is the old one followed by the whole block.
         CarryItem ci;
-        ci.head = (uint64_t)(uintptr_t)st.carry[st.cur];
+        ci.head = ch.src;
         ci.head_len = (int32_t)c;
         ci.body = (uint64_t)(uintptr_t)t.block;
         ci.dst = (uint64_t)(uintptr_t)st.carry[st.cur ^ 1];
-        ci.from = (int32_t)emitted;
+        ci.from = 0;
         ci.count = (int32_t)newc;
         ci.elem = elem;
-        carries.push_back(ci);
+        L.carries.push_back(ci);
         st.cur ^= 1;
+        ch.src = ci.dst;
+        ch.in_buffer = true;
+        ch.open = false;
+    } else if (newc > 0) {
+        // The new carry is the tail of this block (or, for an empty block,
+        // still the old carry).
+        if (n > 0) {
+            ch.src = (uint64_t)(uintptr_t)t.block + (uint64_t)((n - newc) * elem);
+            ch.in_buffer = false;
+        }
+    } else {
+        ch.src = (uint64_t)(uintptr_t)st.carry[st.cur];
+        ch.in_buffer = true;
     }
+    ch.len = (int32_t)newc;
     st.carry_len = (int32_t)newc;
     st.next_abs += emitted;
     t.emitted_samples = emitted;
     t.emitted_windows = nw;
+}
+
+// End of a stream's part of a batch: a carry left inside a block is copied
+// to the stream's other carry buffer (after the batch's filter launch).
+void close_chain(rfi_server* srv, SrvStream& st, Chain& ch, Lane& L)
+{
+    if (ch.len > 0 && !ch.in_buffer) {
+        CarryItem ci;
+        ci.head = ch.src;
+        ci.head_len = ch.len;
+        ci.body = 0;
+        ci.dst = (uint64_t)(uintptr_t)st.carry[st.cur ^ 1];
+        ci.from = 0;
+        ci.count = ch.len;
+        ci.elem = srv->cfg.elem_size;
+        L.carries.push_back(ci);
+        st.cur ^= 1;
+    }
 }
 
 // Launches one batch on a lane if it has pending blocks and a free slot.
@@ -245,31 +300,48 @@ int dispatch_lane(rfi_server* srv, int li)
             break;
         }
     if (si < 0 || L.members.empty()) return RFI_OK;
-    std::vector<StreamDesc> descs;
-    std::vector<Item> items;
-    std::vector<CarryItem> carries;
-    std::vector<uint64_t> batch;
+    L.descs.clear();
+    L.items.clear();
+    L.carries.clear();
+    L.batch.clear();
     const int nm = (int)L.members.size();
-    for (int j = 0; j < nm && (int)batch.size() < srv->cfg.max_batch; ++j) {
-        const uint32_t sid = L.members[(L.rr + j) % nm];
-        SrvStream& st = srv->streams[sid];
-        if (st.pending.empty()) continue;
-        const uint64_t tk = st.pending.front();
-        st.pending.pop_front();
-        TicketRec& t = srv->tickets[tk - 1];
-        plan_block(srv, st, sid, t, descs, items, carries);
-        t.state = kDispatched;
-        batch.push_back(tk);
+    L.chains.assign(nm, Chain());
+    for (int j = 0; j < nm; ++j) {
+        const SrvStream& st = srv->streams[L.members[j]];
+        L.chains[j].src = (uint64_t)(uintptr_t)st.carry[st.cur];
+        L.chains[j].len = st.carry_len;
     }
-    if (batch.empty()) return RFI_OK;
+    // Round-robin passes: each pass takes the next block of every stream
+    // whose chain is still open.
+    bool progress = true;
+    while (progress && (int)L.batch.size() < srv->cfg.max_batch) {
+        progress = false;
+        for (int jj = 0; jj < nm && (int)L.batch.size() < srv->cfg.max_batch; ++jj) {
+            const int j = (L.rr + jj) % nm;
+            const uint32_t sid = L.members[j];
+            SrvStream& st = srv->streams[sid];
+            if (st.pending.empty() || !L.chains[j].open) continue;
+            const uint64_t tk = st.pending.front();
+            st.pending.pop_front();
+            TicketRec& t = srv->tickets[tk - 1];
+            plan_block(srv, st, sid, t, L.chains[j], L);
+            t.state = kDispatched;
+            L.batch.push_back(tk);
+            progress = true;
+        }
+    }
+    if (L.batch.empty()) return RFI_OK;
+    for (int j = 0; j < nm; ++j) close_chain(srv, srv->streams[L.members[j]], L.chains[j], L);
     L.rr = (L.rr + 1) % nm;
     Slot& sl = L.slots[si];
     StreamDesc* dd = nullptr;
     Item* di = nullptr;
     CarryItem* dc = nullptr;
-    int rc = upload(sl, descs, items, carries, L.s, &dd, &di, &dc);
+    int rc = upload(sl, L.descs, L.items, L.carries, L.s, &dd, &di, &dc);
     if (rc != RFI_OK) return rc;
     hipError_t e = hipSuccess;
+    const std::vector<Item>& items = L.items;
+    const std::vector<CarryItem>& carries = L.carries;
     if (!items.empty()) {
         LaunchArgs a;
         std::memset(&a, 0, sizeof(a));
@@ -291,7 +363,7 @@ int dispatch_lane(rfi_server* srv, int li)
     if (e == hipSuccess) e = hipEventRecord(sl.ev, L.s);
     if (e != hipSuccess) return hip_fail(e);
     sl.busy = true;
-    sl.tickets = std::move(batch);
+    sl.tickets.assign(L.batch.begin(), L.batch.end());
     L.inflight.push_back(si);
     return RFI_OK;
 }
@@ -406,11 +478,15 @@ int rfi_server_create(const rfi_server_config* cfg, rfi_server** out)
     srv->lanes.resize(cfg->n_lanes);
     for (auto& L : srv->lanes) {
         hipError_t e = hipStreamCreateWithFlags(&L.s, hipStreamNonBlocking);
-        for (int s = 0; s < kSlotsPerLane && e == hipSuccess; ++s)
+        int rc = RFI_OK;
+        for (int s = 0; s < kSlotsPerLane && e == hipSuccess && rc == RFI_OK; ++s) {
             e = hipEventCreateWithFlags(&L.slots[s].ev, hipEventDisableTiming);
-        if (e != hipSuccess) {
+            // Growing a slot later synchronises the device; start large.
+            if (e == hipSuccess) rc = ensure_slot(L.slots[s], kSlotPrealloc);
+        }
+        if (e != hipSuccess || rc != RFI_OK) {
             rfi_server_destroy(srv);
-            return hip_fail(e);
+            return e != hipSuccess ? hip_fail(e) : rc;
         }
     }
     *out = srv;

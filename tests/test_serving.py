@@ -106,7 +106,8 @@ class Served:
         return n
 
     def result(self, sid):
-        y = np.concatenate(self.outs[sid]) if self.outs[sid] else np.zeros(0, self.dtype)
+        npdt = np.int8 if self.dtype == torch.int8 else np.int16
+        y = np.concatenate(self.outs[sid]) if self.outs[sid] else np.zeros(0, npdt)
         st = np.concatenate(self.stats[sid]) if self.stats[sid] else np.zeros(0, rfi.STATS_DTYPE)
         return y, st
 
@@ -444,4 +445,48 @@ def test_replay_poisson(gpu):
         assert_same(y, st, yo[i], sto[i], f"replayed stream {i}")
     c = srv.counters()
     assert c["completed"] == len(ev)
+    srv.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("max_batch", [5, 64])
+def test_burst_batches_chain_carries(gpu, max_batch):
+    """Every block ready at once: the first batches hold several blocks of
+    one stream, whose head windows read the previous block's tail in the
+    same launch, including blocks shorter than a window."""
+    specs = mixed_specs()
+    rng = np.random.default_rng(41)
+    for s in specs:
+        s.length = 70_000
+    xs = make_streams(specs, SEED + 5)
+    yo, sto = oracle_streams(xs, specs, SEED + 5)
+    srv = rfi.Server(elem_size=1, max_streams=len(specs), max_inflight=4096, max_batch=max_batch,
+                     hbm_budget_bytes=1 << 32, seed=SEED + 5, n_lanes=2)
+    for i, s in enumerate(specs):
+        srv.add_stream(i, s.window, s.k, s.mode)
+    ev = []
+    for i in range(len(specs)):
+        pos = 0
+        for n in split_sizes(70_000, rng, [100, 2000, 4096, 9000, 16384, 33]):
+            ev.append((i, pos, n))
+            pos += n
+    blocks = [torch.from_numpy(xs[i][p:p + n].copy()).to(gpu) for i, p, n in ev]
+    outs = [torch.full((n + specs[i].window - 1,), 0x5A, dtype=torch.int8, device=gpu)
+            for i, p, n in ev]
+    stats = [torch.full(((n + 2 * specs[i].window - 2) // specs[i].window, 4), -7,
+                        dtype=torch.int32, device=gpu) for i, p, n in ev]
+    lat, em = srv.replay([e[0] for e in ev], [0] * len(ev), blocks, outs, stats)
+    c = srv.counters()
+    assert c["launches"] < len(ev)  # several blocks per batch
+    ys = {i: [] for i in range(len(specs))}
+    sts = {i: [] for i in range(len(specs))}
+    for (i, _, _), o, st, e in zip(ev, outs, stats, em):
+        ys[i].append(o[:e].cpu().numpy())
+        sts[i].append(rfi.stats_numpy(st[:e // specs[i].window]))
+    drv = Served(srv, gpu, specs, torch.int8)
+    for i in range(len(specs)):
+        drv.flush(i)
+        fy, fs = drv.result(i)
+        assert_same(np.concatenate(ys[i] + [fy]), np.concatenate(sts[i] + [fs]), yo[i], sto[i],
+                    f"burst stream {i} W={specs[i].window}")
     srv.close()
