@@ -158,7 +158,8 @@ int rfi_plan_execute(rfi_plan* plan, const void* x, void* y, rfi_window_stats* s
  *                         loads overlap the first tile's work) or 0 (use
  *                         the autotuned value, default 1).
  *   RFI_OPT_WG_PER_CU     at most this many workgroups resident per compute
- *                         unit (1..32, enforced by padding LDS), 0 = no cap. */
+ *                         unit (1..32, enforced by padding LDS), 0 = no cap,
+ *                         -1 = the autotuned value (default; 8 untuned). */
 typedef enum { RFI_OPT_TILES_PER_WG = 1, RFI_OPT_WG_PER_CU = 2 } rfi_option;
 int rfi_plan_set_option(rfi_plan* plan, int32_t option, int32_t value);
 /* Number of kernel launches one execute makes, and total windows. */

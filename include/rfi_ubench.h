@@ -10,7 +10,9 @@
  *   variant  0: 64 bytes per lane as four 16-byte loads (the tile shape of
  *               the filter kernels), one workgroup per 16 KiB;
  *            1: as 0 with non-temporal loads and stores;
- *            2: 16 bytes per lane, grid-stride loop over a persistent grid.
+ *            2: 16 bytes per lane, grid-stride loop over a persistent grid;
+ *            3: as 1, but each lane's 64 bytes contiguous (the four loads
+ *               of a lane 16 bytes apart).
  *   stream   hipStream_t (NULL = null stream).
  * Returns 0, RFI_ERR_INVALID (-1) or RFI_ERR_ALIGN (-2); asynchronous.
  */

@@ -81,6 +81,25 @@ void record_tpw(uint64_t sig, int tpw)
     g_tune_tpw[sig] = tpw;
 }
 
+// Occupancy cap (workgroups per CU).  Without tuning: 8, which measured at
+// or above the uncapped rate for every int8 window class and mode (fewer
+// resident workgroups contend less for LDS banks and the L2).
+constexpr int kDefaultWgPerCu = 8;
+static std::map<uint64_t, int> g_tune_cap;
+
+int tuned_cap(uint64_t sig)
+{
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune_cap.find(sig);
+    return it == g_tune_cap.end() ? kDefaultWgPerCu : it->second;
+}
+
+void record_cap(uint64_t sig, int cap)
+{
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune_cap[sig] = cap;
+}
+
 }  // namespace rfi
 
 // ---------------------------------------------------------------------------
@@ -98,7 +117,8 @@ struct GraphEntry {
     uint64_t x, y, st;
     hipStream_t s;
     int sched;
-    int tpw;
+    int tpw;  // effective tiles per workgroup and occupancy cap at capture
+    int cap;
     hipGraph_t graph;
     hipGraphExec_t exec;
 };
@@ -120,7 +140,7 @@ struct rfi_plan {
     int schedule = RFI_SCHED_AUTO;
     int use_graph = 0;
     int tpw = 0;  // int8 tiles per workgroup in loop-free launches (0: tuned)
-    int wg_per_cu = 0;  // occupancy cap (0: none)
+    int wg_per_cu = -1;  // occupancy cap (0: none, -1: tuned)
     std::vector<PlanLaunch> launches[RFI_SCHED_COUNT];
     std::vector<GraphEntry> graphs;
 };
@@ -145,7 +165,7 @@ static int tile_class(int elem, int32_t w) { return elem == 1 ? i8_tile_class(w)
 static hipError_t run_launch(const rfi_plan* p, const PlanLaunch& l, const LaunchArgs& base,
                              hipStream_t s)
 {
-    set_wg_per_cu(p->wg_per_cu);
+    set_wg_per_cu(p->wg_per_cu >= 0 ? p->wg_per_cu : tuned_cap(plan_signature(p)));
     LaunchArgs a = base;
     a.items = p->ditems + l.first;
     a.n_items = l.count;
@@ -185,14 +205,29 @@ static void build_launches(rfi_plan* p)
     const int64_t n_items = (int64_t)p->hitems.size();
     auto clamp_grid = [](int64_t c) { return (int)std::min<int64_t>(std::max<int64_t>(c, 1), 1 << 30); };
     for (int sched = 0; sched < RFI_SCHED_COUNT; ++sched) p->launches[sched].clear();
+    // Split schedules: one launch for the generic items, and one per (tile
+    // class, mode) pair present, so every tile launch runs a kernel compiled
+    // for a single mode (leaner than one that branches over all three).
     for (int g = 0; g <= ncls; ++g) {
         const int64_t c = gend[g] - gbegin[g];
         if (c == 0) continue;
         const int cls = g - 1;
-        PlanLaunch l{g == 0 ? 1 : 0, cls, gmodes[g], gbegin[g], c, clamp_grid(c)};
-        p->launches[RFI_SCHED_SPLIT].push_back(l);
-        l.grid = (int)std::min<int64_t>(c, persistent_grid(elem, cls, l.modes, false));
-        p->launches[RFI_SCHED_SPLIT_PERSIST].push_back(l);
+        int64_t b = gbegin[g];
+        while (b < gend[g]) {
+            int64_t e = gend[g];
+            int modes = gmodes[g];
+            if (g > 0) {
+                const int m = p->M[p->hitems[b].stream];
+                e = b;
+                while (e < gend[g] && p->M[p->hitems[e].stream] == m) ++e;
+                modes = 1 << m;
+            }
+            PlanLaunch l{g == 0 ? 1 : 0, cls, modes, b, e - b, clamp_grid(e - b)};
+            p->launches[RFI_SCHED_SPLIT].push_back(l);
+            l.grid = (int)std::min<int64_t>(e - b, persistent_grid(elem, cls, l.modes, false));
+            p->launches[RFI_SCHED_SPLIT_PERSIST].push_back(l);
+            b = e;
+        }
     }
     if (n_items > 0) {
         PlanLaunch f{2, -1, 7, 0, n_items, clamp_grid(n_items)};
@@ -234,7 +269,9 @@ int plan_build(int elem, int32_t n, const int64_t* L, const int32_t* W, const fl
     if (hipGetDevice(&p->device) != hipSuccess) p->device = 0;
     const int64_t tile_samples = kTileBytes / elem;
     const int ncls = elem == 1 ? kI8Classes : kI16Classes;
-    std::vector<std::vector<Item>> groups(ncls + 1);
+    // Item order: generic items, then the tiles of class 0, 1, ...; within a
+    // class by mode, then stream, then position.
+    std::vector<std::vector<Item>> groups((ncls + 1) * 3);
     int64_t soff = 0, woff = 0;
     p->hdesc.resize(n);
     for (int s = 0; s < n; ++s) {
@@ -257,7 +294,8 @@ int plan_build(int elem, int32_t n, const int64_t* L, const int32_t* W, const fl
         int64_t first_generic = 0;
         if (cls >= 0) {
             const int64_t nt = L[s] / tile_samples;
-            for (int64_t t = 0; t < nt; ++t) groups[cls + 1].push_back(Item{s, kItemTile, t * tile_samples});
+            auto& grp = groups[(cls + 1) * 3 + M[s]];
+            for (int64_t t = 0; t < nt; ++t) grp.push_back(Item{s, kItemTile, t * tile_samples});
             first_generic = nt * (tile_samples / W[s]);
             p->n_tiles += nt;
         }
@@ -329,9 +367,12 @@ int plan_execute(rfi_plan* p, const void* x, void* y, rfi_window_stats* st, hipS
     base.no_stats = st ? 0 : 1;
     const auto& ls = p->launches[sched];
     if (p->use_graph && s != nullptr && !ls.empty()) {
+        const uint64_t sig = plan_signature(p);
+        const int tpw = p->tpw > 0 ? p->tpw : tuned_tpw(sig);
+        const int cap = p->wg_per_cu >= 0 ? p->wg_per_cu : tuned_cap(sig);
         for (auto& g : p->graphs) {
             if (g.x == base.x_base && g.y == base.y_base && g.st == base.stats_base && g.s == s &&
-                g.sched == sched && g.tpw == p->tpw) {
+                g.sched == sched && g.tpw == tpw && g.cap == cap) {
                 hipError_t e = hipGraphLaunch(g.exec, s);
                 return e == hipSuccess ? RFI_OK : hip_fail(e);
             }
@@ -342,7 +383,7 @@ int plan_execute(rfi_plan* p, const void* x, void* y, rfi_window_stats* st, hipS
             (void)hipGraphDestroy(p->graphs.front().graph);
             p->graphs.erase(p->graphs.begin());
         }
-        GraphEntry g{base.x_base, base.y_base, base.stats_base, s, sched, p->tpw, nullptr, nullptr};
+        GraphEntry g{base.x_base, base.y_base, base.stats_base, s, sched, tpw, cap, nullptr, nullptr};
         hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e);
         hipError_t le = hipSuccess;
@@ -475,7 +516,7 @@ int rfi_plan_set_option(rfi_plan* plan, int32_t option, int32_t value)
         return RFI_OK;
     }
     if (option == RFI_OPT_WG_PER_CU) {
-        if (value < 0 || value > 32) return RFI_ERR_INVALID;
+        if (value < -1 || value > 32) return RFI_ERR_INVALID;
         plan->wg_per_cu = value;
         drop_graphs(plan);
         return RFI_OK;
@@ -514,16 +555,19 @@ int rfi_plan_autotune(rfi_plan* plan, const void* x, void* y, rfi_window_stats* 
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return hip_fail(hipGetLastError());
-    int best = RFI_SCHED_SPLIT, best_tpw = 1;
+    int best = RFI_SCHED_SPLIT, best_tpw = 1, best_cap = kDefaultWgPerCu;
     float best_t = 1e30f;
-    const int saved_tpw = plan->tpw;
-    struct Cand { int sched, tpw; };
-    const Cand cands[] = {{RFI_SCHED_SPLIT, 2}, {RFI_SCHED_SPLIT, 1}, {RFI_SCHED_SPLIT_PERSIST, 1},
-                          {RFI_SCHED_FUSED, 1}, {RFI_SCHED_FUSED_PERSIST, 1}};
+    const int saved_tpw = plan->tpw, saved_cap = plan->wg_per_cu;
+    struct Cand { int sched, tpw, cap; };
+    const Cand cands[] = {{RFI_SCHED_SPLIT, 1, 8}, {RFI_SCHED_SPLIT, 1, 6}, {RFI_SCHED_SPLIT, 1, 0},
+                          {RFI_SCHED_SPLIT, 2, 8}, {RFI_SCHED_SPLIT_PERSIST, 1, 8},
+                          {RFI_SCHED_FUSED, 1, 8}, {RFI_SCHED_FUSED, 1, 0},
+                          {RFI_SCHED_FUSED_PERSIST, 1, 0}};
     for (const Cand& cand : cands) {
         const int c = cand.sched;
         if (plan->launches[c].empty()) continue;
         plan->tpw = cand.tpw;
+        plan->wg_per_cu = cand.cap;
         rc = plan_execute(plan, x, y, stats_out, s, c);  // warm-up (graph capture)
         if (rc != RFI_OK) break;
         std::vector<float> ts;
@@ -544,16 +588,21 @@ int rfi_plan_autotune(rfi_plan* plan, const void* x, void* y, rfi_window_stats* 
             best_t = med;
             best = c;
             best_tpw = cand.tpw;
+            best_cap = cand.cap;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     plan->tpw = saved_tpw;
+    plan->wg_per_cu = saved_cap;
     if (rc != RFI_OK) return rc;
     plan->schedule = best;
     plan->tpw = best_tpw;
+    plan->wg_per_cu = best_cap;
+    drop_graphs(plan);
     record_schedule(plan_signature(plan), best);
     record_tpw(plan_signature(plan), best_tpw);
+    record_cap(plan_signature(plan), best_cap);
     if (best_schedule) *best_schedule = best;
     if (best_ms) *best_ms = best_t;
     return RFI_OK;

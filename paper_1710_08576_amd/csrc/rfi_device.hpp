@@ -54,6 +54,12 @@ __device__ __forceinline__ uint32_t group_incl_scan(uint32_t v)
     return v;
 }
 
+// Bits of a where m is set, of b elsewhere (one v_bfi_b32).
+__device__ __forceinline__ uint32_t bit_select(uint32_t m, uint32_t a, uint32_t b)
+{
+    return (a & m) | (b & ~m);
+}
+
 // Number of lanes of this lane's aligned group of G whose predicate holds.
 template <int G>
 __device__ __forceinline__ int group_count(bool pred)

@@ -518,12 +518,34 @@ __device__ __forceinline__ TileStats i8_tile(const StreamView& d, int64_t first,
         for (int j = 0; j < NWW; ++j)
             reinterpret_cast<uint4*>(h0 + j * kNarrowStride)[lane] = make_uint4(0, 0, 0, 0);
         wave_sync();
+        // A load's 1 KiB lies in at most two windows, so counting load i in
+        // step i would send 32 or 64 lanes of a wave to one histogram and
+        // serialise their same-bin atomics.  Lanes 8g .. 8g+7 (mod 32)
+        // count load (t + g) mod 4 in step t instead: each step then spreads
+        // the wave over up to eight windows.
+        const int g = (lane >> 3) & 3;
+        // Rotate the four loads by g with two masked selects per word (the
+        // masks are opaque so the selects stay bit-field inserts instead of
+        // becoming a per-lane indexed register read).
+        uint32_t m1 = (g & 1) ? ~0u : 0u, m2 = (g & 2) ? ~0u : 0u;
+        asm volatile("" : "+v"(m1), "+v"(m2));
+        uint32_t r[16];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            uint32_t* hh = sm.hist + ((wbase + i * 1024 + lane * 16) / W) * kNarrowStride;
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) r[4 * t + j] = bit_select(m1, v[4 * ((t + 1) & 3) + j], v[4 * t + j]);
+        uint32_t q[16];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) q[4 * t + j] = bit_select(m2, r[4 * ((t + 2) & 3) + j], r[4 * t + j]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int li = (t + g) & 3;
+            uint32_t* hh = sm.hist + ((wbase + li * 1024 + lane * 16) / W) * kNarrowStride;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const uint32_t u = v[4 * i + j] ^ 0x80808080u;
+                const uint32_t u = q[4 * t + j] ^ 0x80808080u;
                 atomicAdd(&hh[u & 0xFFu], 1u);
                 atomicAdd(&hh[(u >> 8) & 0xFFu], 1u);
                 atomicAdd(&hh[(u >> 16) & 0xFFu], 1u);

@@ -6,18 +6,22 @@
 
 namespace rfi {
 
-template <bool NT>
+// LANE_MAJOR: each lane's 64 bytes are contiguous (loads 16 bytes apart);
+// otherwise each load instruction of a wave covers 1 KiB contiguously.
+template <bool NT, bool LANE_MAJOR = false>
 __global__ __launch_bounds__(256) void k_copy_tile(const uint8_t* __restrict__ x, uint8_t* __restrict__ y)
 {
-    const size_t base = (size_t)blockIdx.x * 16384 + (threadIdx.x >> 6) * 4096 + (threadIdx.x & 63) * 16;
+    constexpr int kLaneStride = LANE_MAJOR ? 64 : 16;
+    constexpr int kLoadStride = LANE_MAJOR ? 16 : 1024;
+    const size_t base = (size_t)blockIdx.x * 16384 + (threadIdx.x >> 6) * 4096 + (threadIdx.x & 63) * kLaneStride;
     uint4 v[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         if constexpr (NT) {
-            const u32x4 t = __builtin_nontemporal_load((const u32x4*)(x + base + i * 1024));
+            const u32x4 t = __builtin_nontemporal_load((const u32x4*)(x + base + i * kLoadStride));
             v[i] = make_uint4(t.x, t.y, t.z, t.w);
         } else {
-            v[i] = gload16(x + base + i * 1024);
+            v[i] = gload16(x + base + i * kLoadStride);
         }
     }
 #pragma unroll
@@ -28,9 +32,9 @@ __global__ __launch_bounds__(256) void k_copy_tile(const uint8_t* __restrict__ x
             t.y = v[i].y;
             t.z = v[i].z;
             t.w = v[i].w;
-            __builtin_nontemporal_store(t, (u32x4*)(y + base + i * 1024));
+            __builtin_nontemporal_store(t, (u32x4*)(y + base + i * kLoadStride));
         } else {
-            gstore16(y + base + i * 1024, v[i]);
+            gstore16(y + base + i * kLoadStride, v[i]);
         }
     }
 }
@@ -46,7 +50,7 @@ __global__ __launch_bounds__(256) void k_copy_stride(const uint8_t* __restrict__
 
 extern "C" int rfi_ubench_copy(const void* x, void* y, uint64_t bytes, int32_t variant, void* stream)
 {
-    if (!x || !y || bytes == 0 || bytes % 16384 != 0 || variant < 0 || variant > 2) return -1;
+    if (!x || !y || bytes == 0 || bytes % 16384 != 0 || variant < 0 || variant > 3) return -1;
     if (((uintptr_t)x | (uintptr_t)y) & 15u) return -2;
     const uint8_t* xs = static_cast<const uint8_t*>(x);
     uint8_t* ys = static_cast<uint8_t*>(y);
@@ -56,6 +60,10 @@ extern "C" int rfi_ubench_copy(const void* x, void* y, uint64_t bytes, int32_t v
     if (tiles > (1u << 30)) return -1;
     if (variant == 0) hipLaunchKernelGGL(rfi::k_copy_tile<false>, dim3((unsigned)tiles), dim3(256), 0, s, xs, ys);
     else if (variant == 1) hipLaunchKernelGGL(rfi::k_copy_tile<true>, dim3((unsigned)tiles), dim3(256), 0, s, xs, ys);
+    else if (variant == 3) {
+        auto k = rfi::k_copy_tile<true, true>;
+        hipLaunchKernelGGL(k, dim3((unsigned)tiles), dim3(256), 0, s, xs, ys);
+    }
     else {
         int dev = 0, cus = 256;
         if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
