@@ -278,6 +278,15 @@ __device__ __forceinline__ uint32_t nonzero_half_mask(uint32_t diff)
     return (h << 1) - (h >> 15);
 }
 
+// |a - b| of the two int16 halves, as uint16 halves (0 .. 65535).
+__device__ __forceinline__ uint32_t pk_absdiff_i16(uint32_t a, uint32_t b)
+{
+    const short2v x = __builtin_bit_cast(short2v, a), y = __builtin_bit_cast(short2v, b);
+    const ushort2v hi = __builtin_bit_cast(ushort2v, __builtin_elementwise_max(x, y));
+    const ushort2v lo = __builtin_bit_cast(ushort2v, __builtin_elementwise_min(x, y));
+    return __builtin_bit_cast(uint32_t, (ushort2v)(hi - lo));
+}
+
 __device__ __forceinline__ uint32_t rep_i16(int v)
 {
     const uint32_t h = (uint32_t)v & 0xFFFFu;

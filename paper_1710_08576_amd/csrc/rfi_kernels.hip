@@ -746,15 +746,77 @@ __device__ __forceinline__ uint4 noise_chunk_i16(uint64_t j0, uint64_t seed, uin
     return make_uint4(o[0], o[1], o[2], o[3]);
 }
 
+// int16 tile: radix selection with a 12-bit coarse digit and a 4-bit fine
+// digit.  Sample values of a noise-dominated window sit within a few
+// hundred of the median, so a coarse pass over the top 8 bits would send
+// almost every sample to a handful of bins and serialise the LDS atomics;
+// 4096 coarse bins (16 values each) spread them over hundreds.
+constexpr int kI16Reps = 2;  // replicas of the coarse histogram (lane & 1)
+
 struct I16TileSmem {
-    static constexpr int R = 8;
-    uint32_t h1[256 * R];  // high digit of x + 32768
-    uint32_t h2[256];      // low digit of x + 32768 inside the median bucket
-    uint32_t h3[256 * R];  // high digit of |x - m|
-    uint32_t h4[256];      // low digit of |x - m| inside the MAD bucket
+    uint32_t h[4096 * kI16Reps];  // coarse counts, bin-major: h[bin * R + rep]
+    uint32_t fine[2][16];         // fine digit inside the selected coarse bin
+    uint32_t part[4];             // per-wave totals of the block scan
+    int sel[2];                   // selected coarse bin, count below it
     uint32_t flagged;
     NoiseScratch ns;
 };
+
+// Coarse bin holding rank `need` (1-based) of the 4096-bin histogram h, and
+// the count of samples in lower bins, for the whole workgroup.  Thread t
+// sums bins 16t .. 16t+15 over the replicas; ends with a barrier after
+// which every thread may read sm.sel.
+__device__ __forceinline__ void i16_coarse_select(I16TileSmem& sm, uint32_t need)
+{
+    constexpr int R = kI16Reps;
+    const int tid = (int)threadIdx.x;
+    const int lane = lane_id(), wave = tid >> 6;
+    const uint32_t* p = sm.h + tid * 16 * R;
+    uint32_t c[16];
+#pragma unroll
+    for (int j = 0; j < 16 * R; j += 4) {
+        const uint4 t = *reinterpret_cast<const uint4*>(p + j);
+        const uint32_t w[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int bin = (j + q) / R;
+            if ((j + q) % R == 0) c[bin] = w[q];
+            else c[bin] += w[q];
+        }
+    }
+#pragma unroll
+    for (int j = 1; j < 16; ++j) c[j] += c[j - 1];
+    const uint32_t incl = group_incl_scan<64>(c[15]);
+    if (lane == 63) sm.part[wave] = incl;
+    __syncthreads();
+    uint32_t off = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) off += w < wave ? sm.part[w] : 0u;
+    const uint32_t excl = off + incl - c[15];
+    if (excl < need && need <= excl + c[15]) {
+        int cnt = 0;
+        uint32_t below = excl;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const uint32_t C = excl + c[j];
+            cnt += C < need ? 1 : 0;
+            below = C < need ? C : below;
+        }
+        sm.sel[0] = tid * 16 + cnt;
+        sm.sel[1] = (int)below;
+    }
+    __syncthreads();
+}
+
+// Fine digit (0..15) holding rank `need` of the 16-bin histogram f; every
+// wave computes it (no barrier).
+__device__ __forceinline__ int i16_fine_select(const uint32_t* f, uint32_t need)
+{
+    const int lane = lane_id();
+    const uint32_t c = group_incl_scan<16>(lane < 16 ? f[lane & 15] : 0u);
+    const uint64_t lt = __ballot(lane < 16 && c < need);
+    return (int)__popcll(lt & 0xFFFFull);
+}
 
 __device__ __forceinline__ int lo16(uint32_t v) { return (int)(int16_t)(v & 0xFFFFu); }
 __device__ __forceinline__ int hi16(uint32_t v) { return (int)(int16_t)(v >> 16); }
@@ -763,11 +825,10 @@ __device__ __forceinline__ int hi16(uint32_t v) { return (int)(int16_t)(v >> 16)
 __device__ void i16_tile_8192(const StreamView& d, int64_t first, uint64_t seed, I16TileSmem& sm)
 {
     constexpr int W = 8192;
-    constexpr int R = I16TileSmem::R;
+    constexpr int R = kI16Reps;
     const int lane = lane_id();
-    const int wave = (int)(threadIdx.x >> 6);
     const int tid = (int)threadIdx.x;
-    const int wbase = wave * 4096;  // bytes
+    const int wbase = (tid >> 6) * 4096;  // bytes
     const uint8_t* xt = reinterpret_cast<const uint8_t*>(static_cast<const int16_t*>(d.x) + first) + wbase + lane * 16;
     uint8_t* yt = reinterpret_cast<uint8_t*>(static_cast<int16_t*>(d.y) + first) + wbase + lane * 16;
 
@@ -780,63 +841,71 @@ __device__ void i16_tile_8192(const StreamView& d, int64_t first, uint64_t seed,
         v[4 * i + 2] = t.z;
         v[4 * i + 3] = t.w;
     }
-    __syncthreads();
-    zero_words(sm.h1, 256 * R, tid, kBlock);
-    zero_words(sm.h3, 256 * R, tid, kBlock);
-    zero_words(sm.h2, 256, tid, kBlock);
-    zero_words(sm.h4, 256, tid, kBlock);
+    __syncthreads();  // the previous tile is done with the scratch
+    zero_words(sm.h, 4096 * R, tid, kBlock);
+    if (tid < 8) reinterpret_cast<uint4*>(&sm.fine[0][0])[tid] = make_uint4(0, 0, 0, 0);
     if (tid == 0) sm.flagged = 0;
     __syncthreads();
 
-    const int rep = lane & (R - 1);
-    // Digit 1 of x + 32768.
+    uint32_t* hr = sm.h + (lane & (R - 1));
+    // Coarse digit of x + 32768: bits 4..15.
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const uint32_t u = v[q] ^ 0x80008000u;
-        atomicAdd(&sm.h1[((u >> 8) & 0xFFu) * R + rep], 1u);
-        atomicAdd(&sm.h1[(u >> 24) * R + rep], 1u);
+        atomicAdd(hr + ((u >> 4) & 0xFFFu) * R, 1u);
+        atomicAdd(hr + (u >> 20) * R, 1u);
         sched_fence();
     }
     __syncthreads();
     constexpr uint32_t need = (W - 1) / 2 + 1;
-    int b1;
-    uint32_t below1;
-    bucket_of<R>(sm.h1, need, b1, below1);
-    // Digit 2 inside bucket b1.
+    i16_coarse_select(sm, need);
+    const int b1 = sm.sel[0];
+    const uint32_t below1 = (uint32_t)sm.sel[1];
+    // Fine digit inside coarse bin b1.  Words whose samples all lie outside
+    // the bin in every lane are skipped with one wave-uniform test.
+    const uint32_t B1 = ((uint32_t)b1 << 4) | ((uint32_t)b1 << 20);
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const uint32_t u = v[q] ^ 0x80008000u;
-        if ((int)((u >> 8) & 0xFFu) == b1) atomicAdd(&sm.h2[u & 0xFFu], 1u);
-        if ((int)(u >> 24) == b1) atomicAdd(&sm.h2[(u >> 16) & 0xFFu], 1u);
+        const uint32_t t = u ^ B1;
+        const bool in0 = (t & 0xFFF0u) == 0, in1 = (t & 0xFFF00000u) == 0;
+        if (__ballot(in0 || in1) != 0) {
+            if (in0) atomicAdd(&sm.fine[0][u & 0xFu], 1u);
+            if (in1) atomicAdd(&sm.fine[0][(u >> 16) & 0xFu], 1u);
+        }
     }
+    // The coarse counts are consumed: clear them for the |x - m| pass.
+    zero_words(sm.h, 4096 * R, tid, kBlock);
     __syncthreads();
-    int b2;
-    uint32_t below2;
-    bucket_of<1>(sm.h2, need - below1, b2, below2);
-    const int m = ((b1 << 8) | b2) - 32768;
-    // Digits of |x - m| in [0, 65535].
+    const int m = ((b1 << 4) | i16_fine_select(sm.fine[0], need - below1)) - 32768;
+    // |x - m| of both halves, kept for the fine pass.
+    const uint32_t m2 = rep_i16(m);
+    uint32_t dd[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) dd[q] = pk_absdiff_i16(v[q], m2);
+    // Coarse digit of |x - m| in [0, 65535].
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-        const uint32_t d0 = (uint32_t)abs(lo16(v[q]) - m), d1 = (uint32_t)abs(hi16(v[q]) - m);
-        atomicAdd(&sm.h3[(d0 >> 8) * R + rep], 1u);
-        atomicAdd(&sm.h3[(d1 >> 8) * R + rep], 1u);
+        atomicAdd(hr + ((dd[q] >> 4) & 0xFFFu) * R, 1u);
+        atomicAdd(hr + (dd[q] >> 20) * R, 1u);
         sched_fence();
     }
     __syncthreads();
-    int b3;
-    uint32_t below3;
-    bucket_of<R>(sm.h3, need, b3, below3);
+    i16_coarse_select(sm, need);
+    const int b3 = sm.sel[0];
+    const uint32_t below3 = (uint32_t)sm.sel[1];
+    const uint32_t B3 = ((uint32_t)b3 << 4) | ((uint32_t)b3 << 20);
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-        const uint32_t d0 = (uint32_t)abs(lo16(v[q]) - m), d1 = (uint32_t)abs(hi16(v[q]) - m);
-        if ((int)(d0 >> 8) == b3) atomicAdd(&sm.h4[d0 & 0xFFu], 1u);
-        if ((int)(d1 >> 8) == b3) atomicAdd(&sm.h4[d1 & 0xFFu], 1u);
+        const uint32_t t = dd[q] ^ B3;
+        const bool in0 = (t & 0xFFF0u) == 0, in1 = (t & 0xFFF00000u) == 0;
+        if (__ballot(in0 || in1) != 0) {
+            if (in0) atomicAdd(&sm.fine[1][dd[q] & 0xFu], 1u);
+            if (in1) atomicAdd(&sm.fine[1][(dd[q] >> 16) & 0xFu], 1u);
+        }
     }
     __syncthreads();
-    int b4;
-    uint32_t below4;
-    bucket_of<1>(sm.h4, need - below3, b4, below4);
-    const int D = (b3 << 8) | b4;
+    const int D = (b3 << 4) | i16_fine_select(sm.fine[1], need - below3);
 
     float sig;
     const float t = threshold_of(D, d.k, sig);
