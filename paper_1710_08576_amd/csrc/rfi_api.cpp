@@ -106,7 +106,7 @@ void record_cap(uint64_t sig, int cap)
 // Plans.
 // ---------------------------------------------------------------------------
 struct PlanLaunch {
-    int kind;   // 0 tiles of one class, 1 generic, 2 fused
+    int kind;   // 0 tiles of one class, 1 generic, 2 fused (mode-major items)
     int cls;    // tile class for kind 0
     int modes;  // bit m: some stream of the launch uses mode m
     int64_t first, count;
@@ -134,8 +134,10 @@ struct rfi_plan {
     std::vector<int32_t> M;
     std::vector<StreamDesc> hdesc;
     std::vector<Item> hitems;
+    std::vector<Item> hitems_fused;  // the same items, mode-major (fused launches)
     StreamDesc* ddesc = nullptr;
     Item* ditems = nullptr;
+    Item* ditems_fused = nullptr;
     int64_t n_windows = 0, n_tiles = 0, n_generic = 0;
     int schedule = RFI_SCHED_AUTO;
     int use_graph = 0;
@@ -167,12 +169,12 @@ static hipError_t run_launch(const rfi_plan* p, const PlanLaunch& l, const Launc
 {
     set_wg_per_cu(p->wg_per_cu >= 0 ? p->wg_per_cu : tuned_cap(plan_signature(p)));
     LaunchArgs a = base;
-    a.items = p->ditems + l.first;
+    a.items = (l.kind == 2 ? p->ditems_fused : p->ditems) + l.first;
     a.n_items = l.count;
     if (p->elem == 1) {
         if (l.kind == 0) return launch_i8_tiles(l.cls, l.modes, p->tpw > 0 ? p->tpw : tuned_tpw(plan_signature(p)), a, l.grid, s);
         if (l.kind == 1) return launch_i8_generic(a, l.grid, s);
-        return launch_i8_fused(a, l.grid, s);
+        return launch_i8_fused(l.modes, a, l.grid, s);
     }
     if (l.kind == 0) return launch_i16_tiles(l.cls, a, l.grid, s);
     if (l.kind == 1) return launch_i16_generic(a, l.grid, s);
@@ -202,7 +204,6 @@ static void build_launches(rfi_plan* p)
             gend[g] = pos;
         }
     }
-    const int64_t n_items = (int64_t)p->hitems.size();
     auto clamp_grid = [](int64_t c) { return (int)std::min<int64_t>(std::max<int64_t>(c, 1), 1 << 30); };
     for (int sched = 0; sched < RFI_SCHED_COUNT; ++sched) p->launches[sched].clear();
     // Split schedules: one launch for the generic items, and one per (tile
@@ -229,11 +230,27 @@ static void build_launches(rfi_plan* p)
             b = e;
         }
     }
-    if (n_items > 0) {
-        PlanLaunch f{2, -1, 7, 0, n_items, clamp_grid(n_items)};
-        p->launches[RFI_SCHED_FUSED].push_back(f);
-        f.grid = (int)std::min<int64_t>(n_items, persistent_grid(elem, -1, 7, true));
-        p->launches[RFI_SCHED_FUSED_PERSIST].push_back(f);
+    // Fused schedules: one launch per mode present (int8; its kernel is
+    // compiled for that mode), each over every class and the generic items
+    // of that mode; int16 runs them all in one launch.
+    {
+        int64_t b = 0;
+        const int64_t nf = (int64_t)p->hitems_fused.size();
+        while (b < nf) {
+            int64_t e = nf;
+            int modes = 7;
+            if (elem == 1) {
+                const int m = p->M[p->hitems_fused[b].stream];
+                e = b;
+                while (e < nf && p->M[p->hitems_fused[e].stream] == m) ++e;
+                modes = 1 << m;
+            }
+            PlanLaunch f{2, -1, modes, b, e - b, clamp_grid(e - b)};
+            p->launches[RFI_SCHED_FUSED].push_back(f);
+            f.grid = (int)std::min<int64_t>(e - b, persistent_grid(elem, -1, modes, true));
+            p->launches[RFI_SCHED_FUSED_PERSIST].push_back(f);
+            b = e;
+        }
     }
     // One ordinary launch per stream and kind (the plain baseline).
     for (int s = 0; s < p->n; ++s) {
@@ -306,6 +323,14 @@ int plan_build(int elem, int32_t n, const int64_t* L, const int32_t* W, const fl
         woff += nw;
     }
     for (auto& g : groups) p->hitems.insert(p->hitems.end(), g.begin(), g.end());
+    for (int m = 0; m < 3; ++m) {
+        for (const Item& it : groups[0])
+            if (M[it.stream] == m) p->hitems_fused.push_back(it);
+        for (int c = 0; c < ncls; ++c) {
+            const auto& g = groups[(c + 1) * 3 + m];
+            p->hitems_fused.insert(p->hitems_fused.end(), g.begin(), g.end());
+        }
+    }
     if (n > 0) {
         hipError_t e = hipMalloc(&p->ddesc, sizeof(StreamDesc) * n);
         if (e != hipSuccess) return e == hipErrorOutOfMemory ? RFI_ERR_NOMEM : hip_fail(e);
@@ -316,6 +341,11 @@ int plan_build(int elem, int32_t n, const int64_t* L, const int32_t* W, const fl
         hipError_t e = hipMalloc(&p->ditems, sizeof(Item) * p->hitems.size());
         if (e != hipSuccess) return e == hipErrorOutOfMemory ? RFI_ERR_NOMEM : hip_fail(e);
         e = hipMemcpy(p->ditems, p->hitems.data(), sizeof(Item) * p->hitems.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e);
+        e = hipMalloc(&p->ditems_fused, sizeof(Item) * p->hitems_fused.size());
+        if (e != hipSuccess) return e == hipErrorOutOfMemory ? RFI_ERR_NOMEM : hip_fail(e);
+        e = hipMemcpy(p->ditems_fused, p->hitems_fused.data(), sizeof(Item) * p->hitems_fused.size(),
+                      hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(e);
     }
     build_launches(p.get());
@@ -343,6 +373,7 @@ void plan_free(rfi_plan* p)
     if (p->ddesc || p->ditems) (void)hipDeviceSynchronize();
     if (p->ddesc) (void)hipFree(p->ddesc);
     if (p->ditems) (void)hipFree(p->ditems);
+    if (p->ditems_fused) (void)hipFree(p->ditems_fused);
     (void)hipSetDevice(cur);
     delete p;
 }

@@ -118,7 +118,7 @@ __host__ __device__ inline StreamView resolve(const StreamDesc& d, const LaunchA
 // fused: one kernel for all kinds.
 hipError_t launch_i8_tiles(int cls, int modes, int tpw, const LaunchArgs& a, int grid, hipStream_t s);
 hipError_t launch_i8_generic(const LaunchArgs& a, int grid, hipStream_t s);
-hipError_t launch_i8_fused(const LaunchArgs& a, int grid, hipStream_t s);
+hipError_t launch_i8_fused(int modes, const LaunchArgs& a, int grid, hipStream_t s);
 hipError_t launch_i16_tiles(int cls, const LaunchArgs& a, int grid, hipStream_t s);
 hipError_t launch_i16_generic(const LaunchArgs& a, int grid, hipStream_t s);
 hipError_t launch_i16_fused(const LaunchArgs& a, int grid, hipStream_t s);

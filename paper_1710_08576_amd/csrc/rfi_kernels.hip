@@ -267,14 +267,20 @@ __device__ __forceinline__ uint4 noise_chunk_i8(uint64_t j0, uint64_t seed, uint
 // samples) by one thread, so the Philox draws of a workgroup occupy as few
 // waves as the list needs.  cf bit i: slot i of this lane is flagged;
 // merged(wave, lane, slot, x) returns the merged chunk.
+// The list (1 KiB) and the chunks (4 KiB) live in LDS that the tile no
+// longer needs once its windows' parameters are known (its histograms):
+// nothing is written there before the first barrier below, which every
+// wave reaches only after its selection.  The per-wave counts have storage
+// of their own, as they are written before that barrier.
 struct NoiseScratch {
-    uint32_t list[256];
-    uint4 data[256];
-    uint32_t counts[4];
+    uint32_t* counts;  // [4]
+    uint32_t* list;    // [256]
+    uint4* data;       // [256], 16-byte aligned
 };
+constexpr int kNoiseAliasWords = 256 + 4 * 256;
 
 template <class ChunkFn>
-__device__ __forceinline__ void pool_noise(uint32_t (&v)[16], uint32_t cf, NoiseScratch& ns,
+__device__ __forceinline__ void pool_noise(uint32_t (&v)[16], uint32_t cf, const NoiseScratch& ns,
                                            ChunkFn merged)
 {
     const int lane = lane_id();
@@ -345,11 +351,19 @@ struct I8TileSmem {
     static constexpr int kWPW = kWide ? W / 4096 : 1;  // waves per window
     // wide: per-wave replicated histograms; W = 4096 keeps its cumulative
     // counts in replica 0 of its wave, larger W in pc.
-    uint32_t hist[kWide ? 4 * kWaveHistWords : kWin * kNarrowStride];
+    // W = 512 runs its eight windows per wave in two rounds of four.
+    static constexpr int kRounds = W == 512 ? 2 : 1;
+    static constexpr int kHistWords = kWide ? 4 * kWaveHistWords : (kWin / kRounds) * kNarrowStride;
+    static_assert(kHistWords >= kNoiseAliasWords, "noise scratch aliases the histograms");
+    __align__(16) uint32_t hist[kHistWords];
     uint32_t tot[kWPW > 1 ? kWin * 256 : 0];
     uint32_t pc[kWPW > 1 ? kWin * kPadC : 0];
     WinParams prm[kWin];
-    NoiseScratch ns[NS ? 1 : 0];
+    uint32_t noise_counts[NS ? 4 : 0];
+    __device__ NoiseScratch noise()
+    {
+        return NoiseScratch{noise_counts, hist, reinterpret_cast<uint4*>(hist + 256)};
+    }
 };
 
 // Statistics record of one window produced by a tile, written by the caller
@@ -436,7 +450,7 @@ __device__ __forceinline__ void i8_replace(const StreamView& d, int64_t first, u
                                   byte_perm(nz.z, x.z, flag_sel_i8x4(x.z, lo_u, hi_u)),
                                   byte_perm(nz.w, x.w, flag_sel_i8x4(x.w, lo_u, hi_u)));
             };
-            pool_noise(v, cf, sm.ns[0], merged);
+            pool_noise(v, cf, sm.noise(), merged);
         }
     }
 }
@@ -510,60 +524,79 @@ __device__ __forceinline__ TileStats i8_tile(const StreamView& d, int64_t first,
         }
         i8_replace<W, NS, MODE>(d, first, seed, sm, v, [&](int) { return p; });
     } else {
-        // Several windows per wave: one 256-bin histogram of x + 128 per window.
-        constexpr int NWW = 4096 / W;  // windows per wave
-        constexpr int G = 64 / NWW;    // lanes per window in the scan
-        uint32_t* h0 = sm.hist + wave * NWW * kNarrowStride;
-#pragma unroll
-        for (int j = 0; j < NWW; ++j)
-            reinterpret_cast<uint4*>(h0 + j * kNarrowStride)[lane] = make_uint4(0, 0, 0, 0);
-        wave_sync();
+        // Several windows per wave: one 256-bin histogram of x + 128 per
+        // window.  W = 512 takes its eight windows per wave in two rounds
+        // (loads 0-1, then 2-3) to halve the histogram space.
+        constexpr int NWW = 4096 / W;           // windows per wave
+        constexpr int ROUNDS = Smem::kRounds;
+        constexpr int NWR = NWW / ROUNDS;       // windows per round
+        constexpr int LPR = 4 / ROUNDS;         // loads per round
+        constexpr int G = 64 / NWR;             // lanes per window in the scan
+        uint32_t* hwave = sm.hist + wave * NWR * kNarrowStride;
         // A load's 1 KiB lies in at most two windows, so counting load i in
         // step i would send 32 or 64 lanes of a wave to one histogram and
-        // serialise their same-bin atomics.  Lanes 8g .. 8g+7 (mod 32)
-        // count load (t + g) mod 4 in step t instead: each step then spreads
-        // the wave over up to eight windows.
-        const int g = (lane >> 3) & 3;
-        // Rotate the four loads by g with two masked selects per word (the
-        // masks are opaque so the selects stay bit-field inserts instead of
-        // becoming a per-lane indexed register read).
+        // serialise their same-bin atomics.  Lane groups count the loads of
+        // a round in rotated order instead (lanes 8g .. 8g+7 mod 32 start at
+        // load g for four loads per round, lanes 16g .. 16g+15 mod 32 at
+        // load g for two), so each step spreads the wave over more windows.
+        // The rotation uses masked selects with opaque masks, so it stays
+        // bit-field inserts instead of becoming a per-lane indexed read.
+        const int g = LPR == 4 ? (lane >> 3) & 3 : (lane >> 4) & 1;
         uint32_t m1 = (g & 1) ? ~0u : 0u, m2 = (g & 2) ? ~0u : 0u;
         asm volatile("" : "+v"(m1), "+v"(m2));
-        uint32_t r[16];
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
+        for (int r = 0; r < ROUNDS; ++r) {
+            if (r > 0) wave_sync();  // the previous round is done with the histograms
 #pragma unroll
-            for (int j = 0; j < 4; ++j) r[4 * t + j] = bit_select(m1, v[4 * ((t + 1) & 3) + j], v[4 * t + j]);
-        uint32_t q[16];
+            for (int j = 0; j < NWR; ++j)
+                reinterpret_cast<uint4*>(hwave + j * kNarrowStride)[lane] = make_uint4(0, 0, 0, 0);
+            wave_sync();
+            uint32_t q[4 * LPR];
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
+            for (int t = 0; t < LPR; ++t)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) q[4 * t + j] = bit_select(m2, r[4 * ((t + 2) & 3) + j], r[4 * t + j]);
+                for (int j = 0; j < 4; ++j) {
+                    const int l0 = r * LPR + t, l1 = r * LPR + ((t + 1) % LPR);
+                    q[4 * t + j] = bit_select(m1, v[4 * l1 + j], v[4 * l0 + j]);
+                }
+            if constexpr (LPR == 4) {
+                uint32_t q2[16];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int li = (t + g) & 3;
-            uint32_t* hh = sm.hist + ((wbase + li * 1024 + lane * 16) / W) * kNarrowStride;
+                for (int t = 0; t < 4; ++t)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const uint32_t u = q[4 * t + j] ^ 0x80808080u;
-                atomicAdd(&hh[u & 0xFFu], 1u);
-                atomicAdd(&hh[(u >> 8) & 0xFFu], 1u);
-                atomicAdd(&hh[(u >> 16) & 0xFFu], 1u);
-                atomicAdd(&hh[u >> 24], 1u);
-                sched_fence();
+                    for (int j = 0; j < 4; ++j) q2[4 * t + j] = bit_select(m2, q[4 * ((t + 2) & 3) + j], q[4 * t + j]);
+#pragma unroll
+                for (int k = 0; k < 16; ++k) q[k] = q2[k];
+            }
+#pragma unroll
+            for (int t = 0; t < LPR; ++t) {
+                const int li = r * LPR + ((t + g) % LPR);
+                uint32_t* hh = hwave + (((li * 1024 + lane * 16) / W) - r * NWR) * kNarrowStride;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t u = q[4 * t + j] ^ 0x80808080u;
+                    atomicAdd(&hh[u & 0xFFu], 1u);
+                    atomicAdd(&hh[(u >> 8) & 0xFFu], 1u);
+                    atomicAdd(&hh[(u >> 16) & 0xFFu], 1u);
+                    atomicAdd(&hh[u >> 24], 1u);
+                    sched_fence();
+                }
+            }
+            wave_sync();
+            const int wl = wave * NWW + r * NWR + lane / G;
+            uint32_t* hw = hwave + (lane / G) * kNarrowStride;
+            int mb, D;
+            select_i8<G>(hw, need, mb, D);
+            WinParams p;
+            rfi_window_stats ws;
+            params_i8(hw, mb, D, d.k, W, p, ws);
+            // Lane r of the window's group keeps the statistics of round r.
+            if ((lane & (G - 1)) == r) {
+                sm.prm[wl] = p;
+                ts.s = ws;
+                ts.dst = d.stats ? d.stats + first / W + wl : nullptr;
             }
         }
-        wave_sync();
-        const int wl = wave * NWW + lane / G;
-        uint32_t* hw = sm.hist + wl * kNarrowStride;
-        int mb, D;
-        select_i8<G>(hw, need, mb, D);
-        WinParams p;
-        rfi_window_stats ws;
-        params_i8(hw, mb, D, d.k, W, p, ws);
-        if ((lane & (G - 1)) == 0) sm.prm[wl] = p;
-        ts.s = ws;
-        ts.dst = ((lane & (G - 1)) == 0 && d.stats) ? d.stats + first / W + wl : nullptr;
         wave_sync();
         i8_replace<W, NS, MODE>(d, first, seed, sm, v, [&](int i) {
             return sm.prm[(wbase + i * 1024 + lane * 16) / W];
@@ -754,12 +787,16 @@ __device__ __forceinline__ uint4 noise_chunk_i16(uint64_t j0, uint64_t seed, uin
 constexpr int kI16Reps = 2;  // replicas of the coarse histogram (lane & 1)
 
 struct I16TileSmem {
-    uint32_t h[4096 * kI16Reps];  // coarse counts, bin-major: h[bin * R + rep]
-    uint32_t fine[2][16];         // fine digit inside the selected coarse bin
-    uint32_t part[4];             // per-wave totals of the block scan
-    int sel[2];                   // selected coarse bin, count below it
+    __align__(16) uint32_t h[4096 * kI16Reps];  // coarse counts: h[bin * R + rep]
+    uint32_t fine[2][16];  // fine digit inside the selected coarse bin
+    uint32_t part[4];      // per-wave totals of the block scan
+    int sel[2];            // selected coarse bin, count below it
     uint32_t flagged;
-    NoiseScratch ns;
+    uint32_t noise_counts[4];
+    __device__ NoiseScratch noise()
+    {
+        return NoiseScratch{noise_counts, h, reinterpret_cast<uint4*>(h + 256)};
+    }
 };
 
 // Coarse bin holding rank `need` (1-based) of the 4096-bin histogram h, and
@@ -946,7 +983,7 @@ __device__ void i16_tile_8192(const StreamView& d, int64_t first, uint64_t seed,
             return make_uint4((x.x & ~m0) | (nz.x & m0), (x.y & ~m1) | (nz.y & m1),
                               (x.z & ~m2) | (nz.z & m2), (x.w & ~m3) | (nz.w & m3));
         };
-        pool_noise(v, cf, sm.ns, merged);
+        pool_noise(v, cf, sm.noise(), merged);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -1134,20 +1171,26 @@ __global__ __launch_bounds__(kBlock) void k_i8_generic(LaunchArgs a)
     });
 }
 
+template <bool NS>
 union I8FusedSmem {
-    I8TileSmem<512, true> c0;
-    I8TileSmem<1024, true> c1;
-    I8TileSmem<2048, true> c2;
-    I8TileSmem<4096, true> c3;
-    I8TileSmem<8192, true> c4;
-    I8TileSmem<16384, true> c5;
+    I8TileSmem<512, NS> c0;
+    I8TileSmem<1024, NS> c1;
+    I8TileSmem<2048, NS> c2;
+    I8TileSmem<4096, NS> c3;
+    I8TileSmem<8192, NS> c4;
+    I8TileSmem<16384, NS> c5;
     GenericSmem g;
 };
 
-template <bool PERSIST>
+// Every item kind and window class in one launch.  MODES: the modes of the
+// launch's tiles (a kernel compiled for one mode needs fewer registers than
+// one that branches over all three, and registers bound its occupancy);
+// generic items take any mode.
+template <bool PERSIST, int MODES>
 __global__ __launch_bounds__(kBlock) void k_i8_fused(LaunchArgs a)
 {
-    __shared__ I8FusedSmem sm;
+    constexpr bool NS = (MODES & 4) != 0;
+    __shared__ I8FusedSmem<NS> sm;
     for_items<PERSIST>(a, [&](int64_t it) {
         const Item item = a.items[it];
         const StreamView d = resolve(a.streams[item.stream], a);
@@ -1161,12 +1204,12 @@ __global__ __launch_bounds__(kBlock) void k_i8_fused(LaunchArgs a)
         uint32_t v[16];
         tile_load(d, item.first, v);
         switch (i8_tile_class(d.window)) {
-            case 0: write_stats(i8_tile_any<512, true, 7>(d, item.first, a.seed, sm.c0, v)); break;
-            case 1: write_stats(i8_tile_any<1024, true, 7>(d, item.first, a.seed, sm.c1, v)); break;
-            case 2: write_stats(i8_tile_any<2048, true, 7>(d, item.first, a.seed, sm.c2, v)); break;
-            case 3: write_stats(i8_tile_any<4096, true, 7>(d, item.first, a.seed, sm.c3, v)); break;
-            case 4: write_stats(i8_tile_any<8192, true, 7>(d, item.first, a.seed, sm.c4, v)); break;
-            default: write_stats(i8_tile_any<16384, true, 7>(d, item.first, a.seed, sm.c5, v)); break;
+            case 0: write_stats(i8_tile_any<512, NS, MODES>(d, item.first, a.seed, sm.c0, v)); break;
+            case 1: write_stats(i8_tile_any<1024, NS, MODES>(d, item.first, a.seed, sm.c1, v)); break;
+            case 2: write_stats(i8_tile_any<2048, NS, MODES>(d, item.first, a.seed, sm.c2, v)); break;
+            case 3: write_stats(i8_tile_any<4096, NS, MODES>(d, item.first, a.seed, sm.c3, v)); break;
+            case 4: write_stats(i8_tile_any<8192, NS, MODES>(d, item.first, a.seed, sm.c4, v)); break;
+            default: write_stats(i8_tile_any<16384, NS, MODES>(d, item.first, a.seed, sm.c5, v)); break;
         }
     });
 }
@@ -1308,9 +1351,20 @@ hipError_t launch_i8_generic(const LaunchArgs& a, int grid, hipStream_t s)
 {
     return launch(RFI_PICK(k_i8_generic, a, grid), a, grid, s);
 }
-hipError_t launch_i8_fused(const LaunchArgs& a, int grid, hipStream_t s)
+template <bool PERSIST>
+static void (*i8_fused_kernel(int modes))(LaunchArgs)
 {
-    return launch(RFI_PICK(k_i8_fused, a, grid), a, grid, s);
+    switch (modes) {
+        case 1: return k_i8_fused<PERSIST, 1>;
+        case 2: return k_i8_fused<PERSIST, 2>;
+        case 4: return k_i8_fused<PERSIST, 4>;
+        default: return k_i8_fused<PERSIST, 7>;
+    }
+}
+
+hipError_t launch_i8_fused(int modes, const LaunchArgs& a, int grid, hipStream_t s)
+{
+    return launch(grid < a.n_items ? i8_fused_kernel<true>(modes) : i8_fused_kernel<false>(modes), a, grid, s);
 }
 hipError_t launch_i16_tiles(int cls, const LaunchArgs& a, int grid, hipStream_t s)
 {
@@ -1338,7 +1392,7 @@ int persistent_grid(int elem_size, int cls, int modes, bool fused)
 {
     void (*k)(LaunchArgs) = nullptr;
     if (elem_size == 1) {
-        if (fused) k = k_i8_fused<true>;
+        if (fused) k = i8_fused_kernel<true>(modes);
         else if (cls < 0) k = k_i8_generic<true>;
         else k = i8_tile_kernel(cls, modes, true, 1);
     } else {

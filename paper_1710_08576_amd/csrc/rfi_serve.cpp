@@ -352,7 +352,7 @@ int dispatch_lane(rfi_server* srv, int li)
         set_wg_per_cu(0);
         int64_t grid = a.n_items;
         if (srv->cfg.schedule == RFI_SCHED_FUSED_PERSIST) grid = std::min<int64_t>(grid, srv->persist_grid);
-        e = srv->cfg.elem_size == 1 ? launch_i8_fused(a, (int)grid, L.s)
+        e = srv->cfg.elem_size == 1 ? launch_i8_fused(7, a, (int)grid, L.s)
                                     : launch_i16_fused(a, (int)grid, L.s);
         ++srv->n_launches;
     }

@@ -17,6 +17,12 @@ markdown summary with a machine-readable JSON block:
 Usage:  python -m paper_1710_08576_amd.profiling --trace DIR --fetch DIR
         --write DIR --bench FILE --copy-bytes N --out profiles/NAME.md
         --command "..." [--command "..."]
+        python -m paper_1710_08576_amd.profiling --trace DIR --trace-only
+        --title "..." --out profiles/NAME.md --command "..."
+
+The second form summarises a kernel trace alone: launches grouped by kernel
+and grid size (the same kernel runs with different grids in different
+workloads), with their mean durations.
 """
 from __future__ import annotations
 
@@ -100,6 +106,38 @@ def summarize(trace_dir, fetch_dir, write_dir, bench_file, copy_bytes, commands)
     }
 
 
+def trace_by_grid(trace_dir):
+    """{(kernel, workgroups): [durations ns]} from a kernel trace."""
+    out = {}
+    for r in _csv(trace_dir, "_kernel_trace.csv"):
+        name = r["Kernel_Name"]
+        wgs = int(r["Grid_Size_X"]) // max(1, int(r["Workgroup_Size_X"]))
+        dur = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        out.setdefault((name, wgs), []).append(dur)
+    return out
+
+
+def write_trace_markdown(trace_dir, title, commands, out, bench_file=None):
+    groups = trace_by_grid(trace_dir)
+    lines = ["# rocprofv3 kernel trace: " + title, "", "Commands (run from the repository root on one MI355X):", ""]
+    lines += ["    " + c for c in commands]
+    lines += ["", "Launches grouped by kernel and grid (workgroups of 256 threads).", "",
+              "| kernel | workgroups | calls | mean us | min us | max us |", "|---|---|---|---|---|---|"]
+    for (name, wgs), d in sorted(groups.items(), key=lambda kv: (kv[0][0], kv[0][1])):
+        if "rfi::" not in name:
+            continue
+        lines.append(f"| `{name.split('(')[0]}` | {wgs} | {len(d)} | {statistics.mean(d) / 1e3:.1f} | "
+                     f"{min(d) / 1e3:.1f} | {max(d) / 1e3:.1f} |")
+    if bench_file and os.path.exists(bench_file):
+        with open(bench_file) as f:
+            js = [ln for ln in f if ln.strip().startswith("{")]
+        if js:
+            lines += ["", "Bench line printed by the traced run:", "", "    " + js[-1].strip()]
+    lines += ["", "Kernel sources: sha256 " + kernel_source_hash()]
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def write_markdown(summary, out):
     lines = ["# rocprofv3 summary: int8 plain-scale workload (60 x 2^24, window 4096)", ""]
     lines.append("Commands (run from the repository root on one MI355X):")
@@ -147,13 +185,19 @@ def load_summary(path):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", required=True)
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
     ap.add_argument("--bench", default=None)
-    ap.add_argument("--copy-bytes", type=int, required=True)
+    ap.add_argument("--copy-bytes", type=int)
     ap.add_argument("--out", required=True)
     ap.add_argument("--command", action="append", default=[])
+    ap.add_argument("--trace-only", action="store_true")
+    ap.add_argument("--title", default="")
     a = ap.parse_args()
+    if a.trace_only:
+        write_trace_markdown(a.trace, a.title, a.command, a.out, a.bench)
+        print(a.out)
+        return
     s = summarize(a.trace, a.fetch, a.write, a.bench, a.copy_bytes, a.command)
     write_markdown(s, a.out)
     print(a.out)
