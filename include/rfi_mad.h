@@ -22,10 +22,10 @@
  *       RFI_MODE_NOISE  saturate(median + q), q = (s * G[u] + 2^15) >> 16
  *                       (arithmetic shift), s = (int)(1.4826f*D * 256.0f),
  *                       G[u] = round(256 * PhiInv((u + 0.5) / 4096)),
- *                       u = bits [63 - 12c, 52 - 12c] (c = j & 3) of word
- *                       (j >> 2) & 3 of the Philox4x64-10 block (Salmon
- *                       et al., SC'11) with key (seed, stream) and counter
- *                       (j >> 4, 0, 0, 0): one block per 16 samples;
+ *                       u = the 12 most significant bits of word j & 3
+ *                       of the Philox4x64-10 block (Salmon et al.,
+ *                       SC'11) with key (seed, stream) and counter
+ *                       (j >> 2, 0, 0, 0): one block per 4 samples;
  *                       j = absolute sample index within the stream.
  *   - statistics are taken from the input window in every mode.
  *

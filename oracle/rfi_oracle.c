@@ -132,17 +132,17 @@ static int64_t floor_div_65536(int64_t a)
 }
 
 /* Noise offset q(j) for absolute sample index j of stream `stream`.
- * One Philox4x64-10 block (key (seed, stream), counter (j >> 4, 0, 0, 0))
- * serves 16 consecutive samples: word (j >> 2) & 3 of the block holds four
- * 12-bit fields, most significant first, and sample j takes field j & 3. */
+ * One Philox4x64-10 block (key (seed, stream), counter (j >> 2, 0, 0, 0))
+ * serves 4 consecutive samples: sample j takes word j & 3 of the block and
+ * uses its 12 most significant bits as the table index. */
 static int64_t noise_offset(int64_t j, uint32_t stream, uint64_t seed, int32_t sigma_q8)
 {
-    uint64_t ctr[4] = {(uint64_t)j >> 4, 0, 0, 0};
+    uint64_t ctr[4] = {(uint64_t)j >> 2, 0, 0, 0};
     uint64_t key[2] = {seed, (uint64_t)stream};
     uint64_t r[4];
     orc_philox4x64_10(ctr, key, r);
-    uint64_t word = r[(j >> 2) & 3];
-    uint32_t u = (uint32_t)((word >> (52 - 12 * (j & 3))) & 0xFFF);
+    uint64_t word = r[j & 3];
+    uint32_t u = (uint32_t)(word >> 52);
     pthread_once(&g_q8_once, q8_init);
     return floor_div_65536((int64_t)sigma_q8 * (int64_t)g_q8[u] + 32768);
 }

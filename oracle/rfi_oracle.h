@@ -23,8 +23,8 @@
  *   - "constant" replacement is 0 (every experiment in Sec. III uses zeros);
  *   - "digital noise" is m + q, q drawn from a Q8 Gaussian quantile table
  *     scaled by the robust sigma, indexed by a 12-bit field of a
- *     Philox4x64-10 block (Salmon et al., SC'11) keyed by (seed, stream);
- *     one block per 16 consecutive samples at absolute index j >> 4;
+ *     Philox4x64-10 block (Salmon et al., SC'11) keyed by (seed, stream):
+ *     counter j >> 2 for absolute sample index j, word j & 3, top 12 bits;
  *   - a short final window is a window of its own.
  */
 #ifndef RFI_ORACLE_H

@@ -237,37 +237,34 @@ __device__ __forceinline__ void wide_params(const uint32_t* pc, int mb, int D, f
 }
 
 // ---------------------------------------------------------------------------
-// Noise.  One Philox4x64-10 block serves 16 consecutive samples: word
-// (j >> 2) & 3 holds four 12-bit fields, most significant first, and sample
-// j takes field j & 3.  A 16-byte chunk of int8 samples is one block.
+// Noise.  One Philox4x64-10 block (counter j >> 2) serves 4 consecutive
+// samples: sample j takes word j & 3 and indexes the Q8 table with its 12
+// most significant bits.
 // ---------------------------------------------------------------------------
-// 16 int8 noise samples for the chunk whose first absolute index is j0
-// (a multiple of 16): byte c of word w is sample 4w + c.
-__device__ __forceinline__ uint4 noise_chunk_i8(uint64_t j0, uint64_t seed, uint32_t key, int m,
-                                                int sq8)
+// 4 int8 noise samples starting at absolute index j0 (a multiple of 4):
+// byte c is sample j0 + c.
+__device__ __forceinline__ uint32_t noise_quad_i8(uint64_t j0, uint64_t seed, uint32_t key, int m,
+                                                  int sq8)
 {
-    const Philox4x64 r = philox4x64_10(j0 >> 4, seed, key);
-    uint32_t o[4];
+    const Philox4x64 r = philox4x64_10(j0 >> 2, seed, key);
+    uint32_t nb = 0;
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
-        uint32_t nb = 0;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int g = c_q8[(uint32_t)(r.w[w] >> (52 - 12 * c)) & 0xFFFu];
-            const int q = (sq8 * g + 32768) >> 16;  // |sq8 * g| < 2^31 for int8
-            nb |= ((uint32_t)min(max(m + q, -128), 127) & 0xFFu) << (8 * c);
-        }
-        o[w] = nb;
+    for (int c = 0; c < 4; ++c) {
+        const int g = c_q8[(uint32_t)(r.w[c] >> 52)];
+        const int q = (sq8 * g + 32768) >> 16;  // |sq8 * g| < 2^31 for int8
+        nb |= ((uint32_t)min(max(m + q, -128), 127) & 0xFFu) << (8 * c);
     }
-    return make_uint4(o[0], o[1], o[2], o[3]);
+    return nb;
 }
 
-// Flagged 16-byte chunks of a workgroup's tile are pooled into one list;
-// each list entry is turned into its merged chunk (noise in the flagged
-// samples) by one thread, so the Philox draws of a workgroup occupy as few
-// waves as the list needs.  cf bit i: slot i of this lane is flagged;
-// merged(wave, lane, slot, x) returns the merged chunk.
-// The list (1 KiB) and the chunks (4 KiB) live in LDS that the tile no
+// The flagged 4-sample parts (one Philox block each) of a workgroup's tile
+// are pooled into one list, and one thread turns each entry into its
+// merged part (noise in the flagged samples), so the draws of a workgroup
+// occupy as few waves as the list needs and an isolated flagged sample
+// costs one block.  A lane holds 4 load slots of P parts (4 / P dwords
+// each); cf bit (slot * P + part) marks a part holding a flagged sample;
+// merged(wave, lane, slot, part, x) returns the merged part from the input
+// part x.  The list (1 KiB) and the parts (<= 2 KiB) live in LDS that the tile no
 // longer needs once its windows' parameters are known (its histograms):
 // nothing is written there before the first barrier below, which every
 // wave reaches only after its selection.  The per-wave counts have storage
@@ -279,10 +276,18 @@ struct NoiseScratch {
 };
 constexpr int kNoiseAliasWords = 256 + 4 * 256;
 
-template <class ChunkFn>
+template <int P> struct NoisePart;
+template <> struct NoisePart<4> { using T = uint32_t; };
+template <> struct NoisePart<2> { using T = uint2; };
+
+template <int P, class PartFn>
 __device__ __forceinline__ void pool_noise(uint32_t (&v)[16], uint32_t cf, const NoiseScratch& ns,
-                                           ChunkFn merged)
+                                           PartFn merged)
 {
+    using PartT = typename NoisePart<P>::T;
+    constexpr int WPP = 4 / P;  // dwords per part
+    constexpr int C = kBlock;   // parts per round
+    PartT* data = reinterpret_cast<PartT*>(ns.data);
     const int lane = lane_id();
     const int wave = (int)(threadIdx.x >> 6);
     const uint32_t cnt = __popc(cf);
@@ -300,35 +305,39 @@ __device__ __forceinline__ void pool_noise(uint32_t (&v)[16], uint32_t cf, const
     // With no entries the loop below has no barrier: close the counts reads
     // here so no wave reuses the scratch while another still reads it.
     if (F == 0) __syncthreads();
-    for (int r0 = 0; r0 < F; r0 += 256) {
+    for (int r0 = 0; r0 < F; r0 += C) {
         int e = base - r0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            if ((cf >> i) & 1u) {
-                if (e >= 0 && e < 256) {
-                    ns.list[e] = (uint32_t)(wave << 8 | lane << 2 | i);
-                    ns.data[e] = make_uint4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]);
+        for (int q = 0; q < 4 * P; ++q) {
+            if ((cf >> q) & 1u) {
+                if (e >= 0 && e < C) {
+                    ns.list[e] = (uint32_t)(wave << 8 | lane << 2 | (q / P)) | (uint32_t)(q % P) << 16;
+                    if constexpr (P == 4) data[e] = v[q];
+                    else data[e] = make_uint2(v[WPP * q], v[WPP * q + 1]);
                 }
                 ++e;
             }
         }
         __syncthreads();
         const int k = (int)threadIdx.x;
-        if (k < min(256, F - r0)) {
+        if (k < min(C, F - r0)) {
             const uint32_t ent = ns.list[k];
-            ns.data[k] = merged((int)(ent >> 8), (int)((ent >> 2) & 63u), (int)(ent & 3u), ns.data[k]);
+            data[k] = merged((int)((ent >> 8) & 3u), (int)((ent >> 2) & 63u), (int)(ent & 3u),
+                             (int)(ent >> 16), data[k]);
         }
         __syncthreads();
         e = base - r0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            if ((cf >> i) & 1u) {
-                if (e >= 0 && e < 256) {
-                    const uint4 t = ns.data[e];
-                    v[4 * i] = t.x;
-                    v[4 * i + 1] = t.y;
-                    v[4 * i + 2] = t.z;
-                    v[4 * i + 3] = t.w;
+        for (int q = 0; q < 4 * P; ++q) {
+            if ((cf >> q) & 1u) {
+                if (e >= 0 && e < C) {
+                    if constexpr (P == 4) {
+                        v[q] = data[e];
+                    } else {
+                        const uint2 t = data[e];
+                        v[WPP * q] = t.x;
+                        v[WPP * q + 1] = t.y;
+                    }
                 }
                 ++e;
             }
@@ -426,31 +435,27 @@ __device__ __forceinline__ void i8_replace(const StreamView& d, int64_t first, u
         }
     } else {
         static_assert(NS, "noise needs its LDS scratch");
-        uint32_t cf = 0;
+        uint32_t cf = 0;  // bit 4i + j: dword j of slot i holds a flagged sample
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const WinParams p = bounds(i);
             const uint32_t lo = rep_i16(p.lo * 256), hi = rep_i16(p.hi * 256);
-            uint32_t t = 0;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) t |= clamp_i8x4(v[4 * i + j], lo, hi) ^ v[4 * i + j];
-            cf |= (t != 0 ? 1u : 0u) << i;
+            for (int j = 0; j < 4; ++j)
+                cf |= ((clamp_i8x4(v[4 * i + j], lo, hi) ^ v[4 * i + j]) != 0 ? 1u : 0u) << (4 * i + j);
             sched_fence();
         }
         if constexpr (NS) {
             const int64_t abs0 = d.abs_base + first;
             const uint32_t key1 = d.key;
-            auto merged = [&](int wv, int ln, int slot, uint4 x) -> uint4 {
-                const int off = wv * 4096 + slot * 1024 + ln * 16;
+            auto merged = [&](int wv, int ln, int slot, int part, uint32_t x) -> uint32_t {
+                const int off = wv * 4096 + slot * 1024 + ln * 16 + part * 4;
                 const WinParams p = sm.prm[off / W];
                 const uint32_t lo_u = rep_i16((p.lo + 128) * 256), hi_u = rep_i16((p.hi + 128) * 256);
-                const uint4 nz = noise_chunk_i8((uint64_t)(abs0 + off), seed, key1, p.m, p.sq8);
-                return make_uint4(byte_perm(nz.x, x.x, flag_sel_i8x4(x.x, lo_u, hi_u)),
-                                  byte_perm(nz.y, x.y, flag_sel_i8x4(x.y, lo_u, hi_u)),
-                                  byte_perm(nz.z, x.z, flag_sel_i8x4(x.z, lo_u, hi_u)),
-                                  byte_perm(nz.w, x.w, flag_sel_i8x4(x.w, lo_u, hi_u)));
+                const uint32_t nz = noise_quad_i8((uint64_t)(abs0 + off), seed, key1, p.m, p.sq8);
+                return byte_perm(nz, x, flag_sel_i8x4(x, lo_u, hi_u));
             };
-            pool_noise(v, cf, sm.noise(), merged);
+            pool_noise<4>(v, cf, sm.noise(), merged);
         }
     }
 }
@@ -654,9 +659,9 @@ __device__ __forceinline__ int load_logical(const StreamView& d, int64_t i)
 __device__ __forceinline__ int noise_sample(int64_t j, uint64_t seed, uint32_t key, int m, int sq8,
                                             int vmin, int vmax)
 {
-    const Philox4x64 r = philox4x64_10((uint64_t)j >> 4, seed, key);
-    const uint64_t word = pick4(r, (int)((j >> 2) & 3));
-    const int g = c_q8[(uint32_t)(word >> (52 - 12 * (int)(j & 3))) & 0xFFFu];
+    const Philox4x64 r = philox4x64_10((uint64_t)j >> 2, seed, key);
+    const uint64_t word = pick4(r, (int)(j & 3));
+    const int g = c_q8[(uint32_t)(word >> 52)];
     const int64_t q = ((int64_t)sq8 * g + 32768) >> 16;
     return (int)min(max((int64_t)m + q, (int64_t)vmin), (int64_t)vmax);
 }
@@ -751,32 +756,26 @@ __device__ __forceinline__ void zero_words(uint32_t* p, int words, int tid, int 
         *reinterpret_cast<uint4*>(p + i) = make_uint4(0, 0, 0, 0);
 }
 
-// 8 int16 noise samples for the chunk whose first absolute index is j0 (a
-// multiple of 8): half (j0 >> 3) & 1 of its 16-sample Philox block; dword
-// k of the result holds samples 2k (low half) and 2k + 1.
-__device__ __forceinline__ uint4 noise_chunk_i16(uint64_t j0, uint64_t seed, uint32_t key, int m,
-                                                 int sq8)
+// 4 int16 noise samples starting at absolute index j0 (a multiple of 4):
+// dword k holds samples j0 + 2k (low half) and j0 + 2k + 1.
+__device__ __forceinline__ uint2 noise_quad_i16(uint64_t j0, uint64_t seed, uint32_t key, int m,
+                                                int sq8)
 {
-    const Philox4x64 r = philox4x64_10(j0 >> 4, seed, key);
-    const bool upper = ((j0 >> 3) & 1) != 0;
-    const uint64_t wlo = upper ? r.w[2] : r.w[0];
-    const uint64_t whi = upper ? r.w[3] : r.w[1];
-    uint32_t o[4];
+    const Philox4x64 r = philox4x64_10(j0 >> 2, seed, key);
+    uint32_t o[2];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const uint64_t word = k < 2 ? wlo : whi;
+    for (int k = 0; k < 2; ++k) {
         uint32_t nb = 0;
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-            const int field = (2 * k + b) & 3;
-            const int g = c_q8[(uint32_t)(word >> (52 - 12 * field)) & 0xFFFu];
+            const int g = c_q8[(uint32_t)(r.w[2 * k + b] >> 52)];
             const int64_t q = ((int64_t)sq8 * g + 32768) >> 16;
             const int val = (int)min(max((int64_t)m + q, (int64_t)-32768), (int64_t)32767);
             nb |= ((uint32_t)val & 0xFFFFu) << (16 * b);
         }
         o[k] = nb;
     }
-    return make_uint4(o[0], o[1], o[2], o[3]);
+    return make_uint2(o[0], o[1]);
 }
 
 // int16 tile: radix selection with a 12-bit coarse digit and a 4-bit fine
@@ -952,38 +951,38 @@ __device__ void i16_tile_8192(const StreamView& d, int64_t first, uint64_t seed,
     const int sq8 = (int)__fmul_rn(sig, 256.0f);
     const int mode = d.mode;
     uint32_t nflag = 0;
-    uint32_t cf = 0;  // bit i: slot i holds a flagged sample
+    uint32_t cf = 0;  // bit 2i + h: dwords 2h, 2h + 1 of slot i hold a flagged sample
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        uint32_t t = 0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int q = 4 * i + j;
-            const uint32_t x = v[q];
-            const uint32_t c = pk_clamp_i16(x, lo2, hi2);
-            const uint32_t mk = nonzero_half_mask(c ^ x);
-            nflag += __popc(mk) >> 4;
-            t |= mk;
-            if (mode == RFI_MODE_CLIP) v[q] = c;
-            else if (mode == RFI_MODE_ZERO) v[q] = x & ~mk;
+        for (int h = 0; h < 2; ++h) {
+            uint32_t t = 0;
+#pragma unroll
+            for (int j = 2 * h; j < 2 * h + 2; ++j) {
+                const int q = 4 * i + j;
+                const uint32_t x = v[q];
+                const uint32_t c = pk_clamp_i16(x, lo2, hi2);
+                const uint32_t mk = nonzero_half_mask(c ^ x);
+                nflag += __popc(mk) >> 4;
+                t |= mk;
+                if (mode == RFI_MODE_CLIP) v[q] = c;
+                else if (mode == RFI_MODE_ZERO) v[q] = x & ~mk;
+            }
+            cf |= (t != 0 ? 1u : 0u) << (2 * i + h);
         }
-        cf |= (t != 0 ? 1u : 0u) << i;
     }
     if (mode == RFI_MODE_NOISE) {
         const int64_t abs0 = d.abs_base + first;
         const uint32_t key1 = d.key;
-        auto merged = [&](int wv, int ln, int slot, uint4 x) -> uint4 {
-            // samples: 2048 per wave, 512 per load slot, 8 per lane
-            const int off = wv * 2048 + slot * 512 + ln * 8;
-            const uint4 nz = noise_chunk_i16((uint64_t)(abs0 + off), seed, key1, m, sq8);
+        auto merged = [&](int wv, int ln, int slot, int part, uint2 x) -> uint2 {
+            // samples: 2048 per wave, 512 per load slot, 8 per lane, 4 per part
+            const int off = wv * 2048 + slot * 512 + ln * 8 + part * 4;
+            const uint2 nz = noise_quad_i16((uint64_t)(abs0 + off), seed, key1, m, sq8);
             const uint32_t m0 = nonzero_half_mask(pk_clamp_i16(x.x, lo2, hi2) ^ x.x);
             const uint32_t m1 = nonzero_half_mask(pk_clamp_i16(x.y, lo2, hi2) ^ x.y);
-            const uint32_t m2 = nonzero_half_mask(pk_clamp_i16(x.z, lo2, hi2) ^ x.z);
-            const uint32_t m3 = nonzero_half_mask(pk_clamp_i16(x.w, lo2, hi2) ^ x.w);
-            return make_uint4((x.x & ~m0) | (nz.x & m0), (x.y & ~m1) | (nz.y & m1),
-                              (x.z & ~m2) | (nz.z & m2), (x.w & ~m3) | (nz.w & m3));
+            return make_uint2((x.x & ~m0) | (nz.x & m0), (x.y & ~m1) | (nz.y & m1));
         };
-        pool_noise(v, cf, sm.noise(), merged);
+        pool_noise<2>(v, cf, sm.noise(), merged);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i)

@@ -228,9 +228,9 @@ void plan_block(rfi_server* srv, SrvStream& st, uint32_t sid, TicketRec& t, Chai
             const int cls = elem == 1 ? i8_tile_class(st.W) : i16_tile_class(st.W);
             const int64_t tile_samples = kTileBytes / elem;
             int64_t first_generic = 0;
-            // Tiles draw noise per 16-byte chunk, so their first sample must
-            // start a 16-sample block of the stream's index space.
-            if (cls >= 0 && (x % 16) == 0 && (y % 16) == 0 && (d.abs_base % 16) == 0) {
+            // Tiles draw noise four samples (one Philox block) at a time from
+            // the tile's first sample on, so that sample must start a block.
+            if (cls >= 0 && (x % 16) == 0 && (y % 16) == 0 && (d.abs_base % 4) == 0) {
                 const int64_t nt = (nb * W) / tile_samples;
                 for (int64_t i = 0; i < nt; ++i) L.items.push_back(Item{ds, kItemTile, i * tile_samples});
                 first_generic = nt * (tile_samples / W);
