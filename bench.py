@@ -182,6 +182,13 @@ def main():
                      "algorithmic_bytes_per_launch": abytes},
     }
 
+    # Streaming ceiling of this GPU: the copy microbenchmark on the same
+    # buffers (one read and one write per byte, the kernels' access shape).
+    stream = torch.cuda.current_stream()
+    copy_ms = _time_events(lambda: rfi._lib.ubench_copy(x, y, 1), max(10, args.steps // 2), stream)
+    copy_gbs = 2 * x.numel() / copy_ms / 1e6
+    out["roofline"]["copy_ceiling"] = round(copy_gbs, 1)
+    out["roofline"]["frac_of_copy"] = round(achieved / copy_gbs, 4)
     if args.with_copy:
         for _ in range(args.steps):
             rfi._lib.ubench_copy(x, y, 1)
@@ -227,10 +234,22 @@ def main():
             done += LENGTH
             s += 1
         out["cpu_baseline"] = {"value": round(done / spent / 1e9, 4), "unit": "Gsamples/s",
-                               "cores": threads, "kind": "oracle",
+                               "cores": threads, "kind": "oracle", "cpu_model": _cpu_model(),
+                               "host_cpus": os.cpu_count(),
                                "sample": "%d of the %d streams (2^24 int8 each, window %d, k 3), "
                                          "modes zero/clip/noise in turn" % (s, N_STREAMS, args.window)}
     print(json.dumps(out))
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def _time_events(fn, iters, stream):

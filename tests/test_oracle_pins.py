@@ -117,6 +117,39 @@ def test_counting_definition_random_int8():
         assert (s["median"], s["mad"]) == (m, D)
 
 
+def test_counting_definition_1e5_windows():
+    """10^5 random int8 windows of N = 1..64: the oracle's median and MAD
+    equal the counting definitions (smallest v with #{x <= v} >= r + 1,
+    smallest d with #{|x - m| <= d} >= r + 1), evaluated vectorised per N."""
+    rng = np.random.default_rng(21)
+    n_of = rng.integers(1, 65, 100_000)
+    wins = []
+    for n in n_of:
+        kind = rng.integers(0, 3)
+        if kind == 0:
+            w = rng.integers(-128, 128, n)
+        elif kind == 1:
+            w = np.clip(np.rint(rng.normal(0, rng.uniform(0.5, 20), n)), -128, 127)
+        else:
+            w = rng.choice([-128, 127, 0, 5, -5], n)
+        wins.append(w.astype(np.int8))
+    _, st = _batch_windows(wins)
+    got_m, got_d = np.asarray(st["median"]), np.asarray(st["mad"])
+    for n in range(1, 65):
+        idx = np.nonzero(n_of == n)[0]
+        X = np.stack([wins[i] for i in idx]).astype(np.int64)  # (c, n)
+        r = (n - 1) // 2
+        rows = np.arange(len(idx))[:, None]
+        h = np.zeros((len(idx), 256), np.int64)
+        np.add.at(h, (np.broadcast_to(rows, X.shape), X + 128), 1)
+        m = np.argmax(np.cumsum(h, 1) >= r + 1, 1) - 128
+        hd = np.zeros((len(idx), 256), np.int64)
+        np.add.at(hd, (np.broadcast_to(rows, X.shape), np.abs(X - m[:, None])), 1)
+        D = np.argmax(np.cumsum(hd, 1) >= r + 1, 1)
+        assert np.array_equal(got_m[idx], m), n
+        assert np.array_equal(got_d[idx], D), n
+
+
 def test_counting_definition_random_int16():
     rng = np.random.default_rng(2)
     wins = [rng.integers(-32768, 32768, int(rng.integers(1, 40))).astype(np.int16)
@@ -324,6 +357,33 @@ def test_noise_statistics():
         both = flag[:-lag] & flag[lag:]
         c = np.corrcoef(a[both], b[both])[0, 1]
         assert abs(c) < 0.01, (lag, c)
+
+
+def test_noise_distribution_chi2():
+    """With k = 0 every sample != m takes m + q; for windows sharing (m, D)
+    the q values must follow the distribution that uniform 12-bit indices
+    induce through the Q8 table and the scale s (chi-square, p > 1e-4)."""
+    W = 64
+    base = np.array([-4] * 8 + [-2] * 16 + [0] * 9 + [2] * 16 + [4] * 15, dtype=np.int8)
+    rng = np.random.default_rng(5)
+    n_win = 1 << 14
+    x = np.concatenate([rng.permutation(base) for _ in range(n_win)])
+    y, st = oracle.filter_batch(x, [len(x)], [W], 0.0, oracle.NOISE, seed=9)
+    assert np.all(st["median"] == 0) and np.all(st["mad"] == 2)
+    sq8 = int(np.float32(np.float32(np.float32(1.4826) * np.float32(2)) * np.float32(256.0)))
+    G = oracle.q8_table().astype(np.int64)
+    qv = (sq8 * G + 32768) // 65536
+    vals, cnt = np.unique(qv, return_counts=True)
+    p = cnt / 4096.0
+    q = y.astype(np.int64)[x != 0]
+    obs = np.array([(q == v).sum() for v in vals])
+    assert obs.sum() == len(q)  # every q is a table value
+    exp = p * len(q)
+    keep = exp >= 5
+    chi2 = (((obs - exp) ** 2) / exp)[keep].sum() + \
+        ((obs[~keep].sum() - exp[~keep].sum()) ** 2 / max(exp[~keep].sum(), 1e-9))
+    df = int(keep.sum())  # kept cells + pooled tail - 1
+    assert chi2 < df + 6 * math.sqrt(2 * df), (chi2, df)
 
 
 # ---------------------------------------------------------------- noise parts
