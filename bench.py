@@ -290,7 +290,9 @@ def bench_batching(args, dev):
                        "k U[2.5,5], mixed modes" % n}
     variants = [("per_stream_launches", "per_stream", False), ("batched_fused_persist_graph",
                                                                "fused_persist", True),
-                ("batched_split_graph", "split", True)]
+                ("batched_split_graph", "split", True),
+                ("batched_split_concurrent_graph", "split_concurrent", True),
+                ("batched_fused_concurrent_graph", "fused_concurrent", True)]
     with torch.cuda.stream(stream):
         for name, sched, graph in variants:
             p = rfi.Plan(1, L, W, K, M, seed=3)

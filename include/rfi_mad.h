@@ -136,7 +136,13 @@ typedef enum {
     RFI_SCHED_FUSED = 3,       /* one launch for every class, one WG per item   */
     RFI_SCHED_PER_STREAM = 4,  /* one ordinary launch per stream (baseline)     */
     RFI_SCHED_FUSED_PERSIST = 5, /* one persistent launch for every class      */
-    RFI_SCHED_COUNT = 6
+    RFI_SCHED_SPLIT_CONCURRENT = 6, /* SPLIT's launches spread over four HIP
+                                    streams (parallel branches of the graph
+                                    when captured), joined on the caller's
+                                    stream                                 */
+    RFI_SCHED_FUSED_CONCURRENT = 7, /* FUSED's per-mode launches on parallel
+                                    streams, joined likewise             */
+    RFI_SCHED_COUNT = 8
 } rfi_schedule;
 
 /* elem_size 1 or 2; arrays as in rfi_mad_filter.  Allocates device work

@@ -12,7 +12,9 @@
  *            1: as 0 with non-temporal loads and stores;
  *            2: 16 bytes per lane, grid-stride loop over a persistent grid;
  *            3: as 1, but each lane's 64 bytes contiguous (the four loads
- *               of a lane 16 bytes apart).
+ *               of a lane 16 bytes apart);
+ *            4: as 1, lanes 8g..8g+7 (mod 32) taking their loads in the
+ *               rotated order (t + g) mod 4.
  *   stream   hipStream_t (NULL = null stream).
  * Returns 0, RFI_ERR_INVALID (-1) or RFI_ERR_ALIGN (-2); asynchronous.
  */

@@ -21,9 +21,10 @@ RFI_OK = 0
 STATUS = {0: "RFI_OK", -1: "RFI_ERR_INVALID", -2: "RFI_ERR_ALIGN", -3: "RFI_ERR_UNSUPPORTED",
           -4: "RFI_ERR_NOMEM", -5: "RFI_ERR_HIP", -6: "RFI_ERR_BUSY"}
 ZERO, CLIP, NOISE = 0, 1, 2
-SCHED_AUTO, SCHED_SPLIT, SCHED_SPLIT_PERSIST, SCHED_FUSED, SCHED_PER_STREAM, SCHED_FUSED_PERSIST = range(6)
+(SCHED_AUTO, SCHED_SPLIT, SCHED_SPLIT_PERSIST, SCHED_FUSED, SCHED_PER_STREAM, SCHED_FUSED_PERSIST,
+ SCHED_SPLIT_CONCURRENT, SCHED_FUSED_CONCURRENT) = range(8)
 SCHEDULES = {"auto": 0, "split": 1, "split_persist": 2, "fused": 3, "per_stream": 4,
-             "fused_persist": 5}
+             "fused_persist": 5, "split_concurrent": 6, "fused_concurrent": 7}
 
 STATS_DTYPE = np.dtype(
     [("median", "<i4"), ("mad", "<i4"), ("n_flagged", "<u4"), ("threshold", "<f4")]

@@ -107,6 +107,7 @@ void record_cap(uint64_t sig, int cap)
 // ---------------------------------------------------------------------------
 struct PlanLaunch {
     int kind;   // 0 tiles of one class, 1 generic, 2 fused (mode-major items)
+    int queue;  // SPLIT_CONCURRENT: 0 = the caller's stream, 1.. = auxiliary streams
     int cls;    // tile class for kind 0
     int modes;  // bit m: some stream of the launch uses mode m
     int64_t first, count;
@@ -145,6 +146,10 @@ struct rfi_plan {
     int wg_per_cu = -1;  // occupancy cap (0: none, -1: tuned)
     std::vector<PlanLaunch> launches[RFI_SCHED_COUNT];
     std::vector<GraphEntry> graphs;
+    // SPLIT_CONCURRENT: auxiliary streams and fork/join events (created on
+    // first use, default priority).
+    hipStream_t aux[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
 };
 
 namespace rfi {
@@ -223,7 +228,7 @@ static void build_launches(rfi_plan* p)
                 while (e < gend[g] && p->M[p->hitems[e].stream] == m) ++e;
                 modes = 1 << m;
             }
-            PlanLaunch l{g == 0 ? 1 : 0, cls, modes, b, e - b, clamp_grid(e - b)};
+            PlanLaunch l{g == 0 ? 1 : 0, 0, cls, modes, b, e - b, clamp_grid(e - b)};
             p->launches[RFI_SCHED_SPLIT].push_back(l);
             l.grid = (int)std::min<int64_t>(e - b, persistent_grid(elem, cls, l.modes, false));
             p->launches[RFI_SCHED_SPLIT_PERSIST].push_back(l);
@@ -245,7 +250,7 @@ static void build_launches(rfi_plan* p)
                 while (e < nf && p->M[p->hitems_fused[e].stream] == m) ++e;
                 modes = 1 << m;
             }
-            PlanLaunch f{2, -1, modes, b, e - b, clamp_grid(e - b)};
+            PlanLaunch f{2, 0, -1, modes, b, e - b, clamp_grid(e - b)};
             p->launches[RFI_SCHED_FUSED].push_back(f);
             f.grid = (int)std::min<int64_t>(e - b, persistent_grid(elem, -1, modes, true));
             p->launches[RFI_SCHED_FUSED_PERSIST].push_back(f);
@@ -265,9 +270,28 @@ static void build_launches(rfi_plan* p)
                 }
             }
             if (b < 0) continue;
-            PlanLaunch l{g == 0 ? 1 : 0, g - 1, 1 << p->M[s], b, e - b, clamp_grid(e - b)};
+            PlanLaunch l{g == 0 ? 1 : 0, 0, g - 1, 1 << p->M[s], b, e - b, clamp_grid(e - b)};
             p->launches[RFI_SCHED_PER_STREAM].push_back(l);
         }
+    }
+    // Concurrent split: SPLIT's launches over four queues, largest first to
+    // the least loaded queue (by items).
+    {
+        std::vector<PlanLaunch> ls = p->launches[RFI_SCHED_SPLIT];
+        std::stable_sort(ls.begin(), ls.end(),
+                         [](const PlanLaunch& a, const PlanLaunch& b) { return a.count > b.count; });
+        int64_t load[4] = {0, 0, 0, 0};
+        for (auto& l : ls) {
+            int q = 0;
+            for (int i = 1; i < 4; ++i)
+                if (load[i] < load[q]) q = i;
+            l.queue = q;
+            load[q] += l.count;
+        }
+        p->launches[RFI_SCHED_SPLIT_CONCURRENT] = ls;
+        std::vector<PlanLaunch> fs = p->launches[RFI_SCHED_FUSED];
+        for (size_t i = 0; i < fs.size(); ++i) fs[i].queue = (int)(i % 4);
+        p->launches[RFI_SCHED_FUSED_CONCURRENT] = fs;
     }
     p->launches[RFI_SCHED_AUTO] = p->launches[RFI_SCHED_SPLIT];
 }
@@ -370,6 +394,11 @@ void plan_free(rfi_plan* p)
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(p->device);
     drop_graphs(p);
+    for (int i = 0; i < 3; ++i) {
+        if (p->aux[i]) (void)hipStreamDestroy(p->aux[i]);
+        if (p->join[i]) (void)hipEventDestroy(p->join[i]);
+    }
+    if (p->fork) (void)hipEventDestroy(p->fork);
     if (p->ddesc || p->ditems) (void)hipDeviceSynchronize();
     if (p->ddesc) (void)hipFree(p->ddesc);
     if (p->ditems) (void)hipFree(p->ditems);
@@ -382,6 +411,40 @@ static int effective_schedule(const rfi_plan* p)
 {
     if (p->schedule != RFI_SCHED_AUTO) return p->schedule;
     return tuned_schedule(plan_signature(p));
+}
+
+// Issues a schedule's launches on s; SPLIT_CONCURRENT forks them over the
+// plan's auxiliary streams and joins them back on s (under capture the
+// fork and join become graph edges).
+static hipError_t run_schedule(rfi_plan* p, const std::vector<PlanLaunch>& ls, const LaunchArgs& base,
+                               hipStream_t s, int sched)
+{
+    if (sched != RFI_SCHED_SPLIT_CONCURRENT && sched != RFI_SCHED_FUSED_CONCURRENT) {
+        for (const auto& l : ls) {
+            hipError_t e = run_launch(p, l, base, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    hipError_t e = hipSuccess;
+    if (!p->fork) e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
+    for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+        if (!p->aux[i]) e = hipStreamCreateWithFlags(&p->aux[i], hipStreamNonBlocking);
+        if (e == hipSuccess && !p->join[i]) e = hipEventCreateWithFlags(&p->join[i], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventRecord(p->fork, s);
+    for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipStreamWaitEvent(p->aux[i], p->fork, 0);
+    for (const auto& l : ls) {
+        if (e != hipSuccess) break;
+        e = run_launch(p, l, base, l.queue == 0 ? s : p->aux[l.queue - 1]);
+    }
+    for (int i = 0; i < 3; ++i) {
+        // join every branch, also after an error, so no branch stays forked
+        hipError_t j = hipEventRecord(p->join[i], p->aux[i]);
+        if (j == hipSuccess) j = hipStreamWaitEvent(s, p->join[i], 0);
+        if (e == hipSuccess) e = j;
+    }
+    return e;
 }
 
 int plan_execute(rfi_plan* p, const void* x, void* y, rfi_window_stats* st, hipStream_t s,
@@ -417,11 +480,7 @@ int plan_execute(rfi_plan* p, const void* x, void* y, rfi_window_stats* st, hipS
         GraphEntry g{base.x_base, base.y_base, base.stats_base, s, sched, tpw, cap, nullptr, nullptr};
         hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e);
-        hipError_t le = hipSuccess;
-        for (const auto& l : ls) {
-            le = run_launch(p, l, base, s);
-            if (le != hipSuccess) break;
-        }
+        const hipError_t le = run_schedule(p, ls, base, s, sched);
         e = hipStreamEndCapture(s, &g.graph);
         if (le != hipSuccess) return hip_fail(le);
         if (e != hipSuccess) return hip_fail(e);
@@ -434,11 +493,8 @@ int plan_execute(rfi_plan* p, const void* x, void* y, rfi_window_stats* st, hipS
         e = hipGraphLaunch(g.exec, s);
         return e == hipSuccess ? RFI_OK : hip_fail(e);
     }
-    for (const auto& l : ls) {
-        hipError_t e = run_launch(p, l, base, s);
-        if (e != hipSuccess) return hip_fail(e);
-    }
-    return RFI_OK;
+    const hipError_t e = run_schedule(p, ls, base, s, sched);
+    return e == hipSuccess ? RFI_OK : hip_fail(e);
 }
 
 }  // namespace rfi
@@ -593,7 +649,8 @@ int rfi_plan_autotune(rfi_plan* plan, const void* x, void* y, rfi_window_stats* 
     const Cand cands[] = {{RFI_SCHED_SPLIT, 1, 8}, {RFI_SCHED_SPLIT, 1, 6}, {RFI_SCHED_SPLIT, 1, 0},
                           {RFI_SCHED_SPLIT, 2, 8}, {RFI_SCHED_SPLIT_PERSIST, 1, 8},
                           {RFI_SCHED_FUSED, 1, 8}, {RFI_SCHED_FUSED, 1, 0},
-                          {RFI_SCHED_FUSED_PERSIST, 1, 0}};
+                          {RFI_SCHED_FUSED_PERSIST, 1, 0}, {RFI_SCHED_SPLIT_CONCURRENT, 1, 8},
+                          {RFI_SCHED_SPLIT_CONCURRENT, 1, 0}, {RFI_SCHED_FUSED_CONCURRENT, 1, 8}};
     for (const Cand& cand : cands) {
         const int c = cand.sched;
         if (plan->launches[c].empty()) continue;

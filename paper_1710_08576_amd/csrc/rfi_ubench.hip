@@ -39,6 +39,21 @@ __global__ __launch_bounds__(256) void k_copy_tile(const uint8_t* __restrict__ x
     }
 }
 
+// As k_copy_tile<true>, but lanes 8g .. 8g+7 (mod 32) take their four
+// loads in the rotated order (t + g) mod 4: each load instruction then
+// covers eight 128-byte segments of four 1 KiB blocks.
+__global__ __launch_bounds__(256) void k_copy_tile_rot(const uint8_t* __restrict__ x, uint8_t* __restrict__ y)
+{
+    const int lane = threadIdx.x & 63;
+    const int g = (lane >> 3) & 3;
+    const size_t base = (size_t)blockIdx.x * 16384 + (threadIdx.x >> 6) * 4096 + lane * 16;
+    u32x4 v[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) v[t] = __builtin_nontemporal_load((const u32x4*)(x + base + ((t + g) & 3) * 1024));
+#pragma unroll
+    for (int t = 0; t < 4; ++t) __builtin_nontemporal_store(v[t], (u32x4*)(y + base + ((t + g) & 3) * 1024));
+}
+
 __global__ __launch_bounds__(256) void k_copy_stride(const uint8_t* __restrict__ x, uint8_t* __restrict__ y,
                                                      size_t n16)
 {
@@ -50,7 +65,7 @@ __global__ __launch_bounds__(256) void k_copy_stride(const uint8_t* __restrict__
 
 extern "C" int rfi_ubench_copy(const void* x, void* y, uint64_t bytes, int32_t variant, void* stream)
 {
-    if (!x || !y || bytes == 0 || bytes % 16384 != 0 || variant < 0 || variant > 3) return -1;
+    if (!x || !y || bytes == 0 || bytes % 16384 != 0 || variant < 0 || variant > 4) return -1;
     if (((uintptr_t)x | (uintptr_t)y) & 15u) return -2;
     const uint8_t* xs = static_cast<const uint8_t*>(x);
     uint8_t* ys = static_cast<uint8_t*>(y);
@@ -60,6 +75,7 @@ extern "C" int rfi_ubench_copy(const void* x, void* y, uint64_t bytes, int32_t v
     if (tiles > (1u << 30)) return -1;
     if (variant == 0) hipLaunchKernelGGL(rfi::k_copy_tile<false>, dim3((unsigned)tiles), dim3(256), 0, s, xs, ys);
     else if (variant == 1) hipLaunchKernelGGL(rfi::k_copy_tile<true>, dim3((unsigned)tiles), dim3(256), 0, s, xs, ys);
+    else if (variant == 4) hipLaunchKernelGGL(rfi::k_copy_tile_rot, dim3((unsigned)tiles), dim3(256), 0, s, xs, ys);
     else if (variant == 3) {
         auto k = rfi::k_copy_tile<true, true>;
         hipLaunchKernelGGL(k, dim3((unsigned)tiles), dim3(256), 0, s, xs, ys);

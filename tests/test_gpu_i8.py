@@ -93,7 +93,7 @@ def test_mixed_batch_all_schedules_and_graphs(gpu):
     specs += [synth.StreamSpec(50000, 3000, 3.0, rfi.NOISE, 10.0, 0.01, 8, 64)]
     x = synth.gen_packed(specs, seed=4, tag=4)
     ref = None
-    for sched in ("split", "split_persist", "fused", "fused_persist", "per_stream"):
+    for sched in ("split", "split_persist", "fused", "fused_persist", "per_stream", "split_concurrent", "fused_concurrent"):
         for graph in (False, True):
             y, st = gpu_run(x, specs, 9, gpu, schedule=sched, graph=graph, repeat=2)
             if ref is None:
