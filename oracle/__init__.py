@@ -62,6 +62,9 @@ def lib():
             f.argtypes = [P, P, ctypes.c_int32, P, P, P, P, ctypes.c_uint64, P,
                           ctypes.c_int32]
             f.restype = ctypes.c_int
+        L.orc_mom_filter_i8.argtypes = [P, P, ctypes.c_int32, P, P, P, P, ctypes.c_int32,
+                                        ctypes.c_uint64, P, ctypes.c_int32]
+        L.orc_mom_filter_i8.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -131,6 +134,32 @@ def filter_batch(x, lengths, windows, k, mode, seed: int = 0, n_threads: int | N
     if n_threads is None:
         n_threads = os.cpu_count() or 1
     rc = f(_ptr(x), _ptr(y), n, _ptr(L), _ptr(W), _ptr(K), _ptr(M), seed, _ptr(st), n_threads)
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return y, st[:total]
+
+
+def mom_filter_batch(x, lengths, windows, k, mode, mom_k: int, seed: int = 0,
+                     n_threads: int | None = None):
+    """Median-of-MAD filter (Eq. (3)) over a packed int8 batch; returns
+    (y, stats[total_windows]).  Padding elements of y are copied from x."""
+    x = np.ascontiguousarray(x)
+    if x.dtype != np.int8:
+        raise TypeError("the median-of-MAD oracle is int8")
+    n = len(lengths)
+    L = np.ascontiguousarray(lengths, dtype=np.int64)
+    W = np.ascontiguousarray(windows, dtype=np.int32)
+    K = np.ascontiguousarray(np.broadcast_to(np.asarray(k, dtype=np.float32), (n,)))
+    M = np.ascontiguousarray(np.broadcast_to(np.asarray(mode, dtype=np.int32), (n,)))
+    _, _, total = layout(L, W)
+    if total < 0:
+        raise ValueError("invalid lengths/windows")
+    y = x.copy()
+    st = np.zeros(max(total, 1), dtype=STATS_DTYPE)
+    if n_threads is None:
+        n_threads = os.cpu_count() or 1
+    rc = lib().orc_mom_filter_i8(_ptr(x), _ptr(y), n, _ptr(L), _ptr(W), _ptr(K), _ptr(M),
+                                 int(mom_k), seed, _ptr(st), n_threads)
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     return y, st[:total]

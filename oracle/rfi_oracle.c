@@ -147,6 +147,10 @@ static int64_t noise_offset(int64_t j, uint32_t stream, uint64_t seed, int32_t s
     return floor_div_65536((int64_t)sigma_q8 * (int64_t)g_q8[u] + 32768);
 }
 
+static void window_apply(const int32_t* X, int32_t* Y, int32_t n, int32_t m, int32_t D,
+                         int32_t D_thr, int64_t abs_start, uint32_t stream, uint64_t seed,
+                         float k, int32_t mode, int32_t vmin, int32_t vmax, orc_stats* st);
+
 /* X, Y: n samples widened to int32; vmin/vmax: the dtype's range. */
 static void window_core(const int32_t* X, int32_t* Y, int32_t n, int64_t abs_start,
                         uint32_t stream, uint64_t seed, float k, int32_t mode,
@@ -165,9 +169,17 @@ static void window_core(const int32_t* X, int32_t* Y, int32_t n, int64_t abs_sta
     qsort(s, (size_t)n, sizeof(int32_t), cmp_i32);
     int32_t D = s[r];
     free(s);
+    window_apply(X, Y, n, m, D, D, abs_start, stream, seed, k, mode, vmin, vmax, st);
+}
 
+/* Eq. (1)-(2) for one window whose median m and MAD D are known, with the
+ * threshold taken from D_thr (D itself, or the median of MADs of Eq. (3)). */
+static void window_apply(const int32_t* X, int32_t* Y, int32_t n, int32_t m, int32_t D,
+                         int32_t D_thr, int64_t abs_start, uint32_t stream, uint64_t seed,
+                         float k, int32_t mode, int32_t vmin, int32_t vmax, orc_stats* st)
+{
     /* Eq. (1): robust sigma 1.4826 * D, threshold n_sigma times it. */
-    float sigma = 1.4826f * (float)D;
+    float sigma = 1.4826f * (float)D_thr;
     float t = k * sigma;
     int32_t T = (int32_t)floorf(t);
     int32_t sigma_q8 = (int32_t)(sigma * 256.0f);
@@ -318,4 +330,124 @@ int orc_filter_i16(const int16_t* x, int16_t* y, int32_t n_streams, const int64_
                    orc_stats* stats, int32_t n_threads)
 {
     return filter_batch(2, x, y, n_streams, lengths, windows, k, mode, seed, stats, n_threads);
+}
+
+/* ------------------------------------------------------------------ */
+/* Median of MADs (Eq. (3)).                                           */
+/* ------------------------------------------------------------------ */
+/* Lower median and MAD of n int8 samples (the definitions of window_core). */
+static void median_mad(const int32_t* X, int32_t n, int32_t* m_out, int32_t* D_out)
+{
+    int32_t* s = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+    int32_t r = (n - 1) / 2;
+    memcpy(s, X, (size_t)n * sizeof(int32_t));
+    qsort(s, (size_t)n, sizeof(int32_t), cmp_i32);
+    int32_t m = s[r];
+    for (int32_t i = 0; i < n; ++i) s[i] = abs(X[i] - m);
+    qsort(s, (size_t)n, sizeof(int32_t), cmp_i32);
+    *m_out = m;
+    *D_out = s[r];
+    free(s);
+}
+
+typedef struct {
+    const int8_t* x;
+    int8_t* y;
+    int32_t n_streams;
+    const int64_t* lengths;
+    const int32_t* windows;
+    const float* k;
+    const int32_t* mode;
+    int32_t mom_k;
+    uint64_t seed;
+    orc_stats* stats;
+    const int64_t* soff;
+    const int64_t* woff;
+    int32_t first, last; /* streams [first, last) */
+} mom_job;
+
+/* One stream: M(x) and D of every window; M_m(w) = lower median of the MADs
+ * of the K windows ending at w (fewer at the stream's start); then Eqs.
+ * (1)-(2) with M_m(w) in place of the window's own D. */
+static void mom_stream(const mom_job* j, int32_t s)
+{
+    const int64_t L = j->lengths[s];
+    const int32_t W = j->windows[s];
+    const int64_t nw = (L + W - 1) / W;
+    if (nw == 0) return;
+    int32_t* med = (int32_t*)malloc((size_t)nw * sizeof(int32_t));
+    int32_t* mad = (int32_t*)malloc((size_t)nw * sizeof(int32_t));
+    int32_t* X = (int32_t*)malloc((size_t)W * sizeof(int32_t));
+    int32_t* Y = (int32_t*)malloc((size_t)W * sizeof(int32_t));
+    int32_t* sorted = (int32_t*)malloc((size_t)j->mom_k * sizeof(int32_t));
+    const int8_t* xs = j->x + j->soff[s];
+    int8_t* ys = j->y + j->soff[s];
+    for (int64_t w = 0; w < nw; ++w) {
+        const int64_t a = w * W;
+        const int32_t n = (int32_t)(L - a < W ? L - a : W);
+        for (int32_t i = 0; i < n; ++i) X[i] = xs[a + i];
+        median_mad(X, n, &med[w], &mad[w]);
+    }
+    for (int64_t w = 0; w < nw; ++w) {
+        const int64_t lo = w + 1 > j->mom_k ? w + 1 - j->mom_k : 0;
+        const int32_t cnt = (int32_t)(w + 1 - lo);
+        memcpy(sorted, mad + lo, (size_t)cnt * sizeof(int32_t));
+        qsort(sorted, (size_t)cnt, sizeof(int32_t), cmp_i32);
+        const int32_t Dm = sorted[(cnt - 1) / 2];
+        const int64_t a = w * W;
+        const int32_t n = (int32_t)(L - a < W ? L - a : W);
+        for (int32_t i = 0; i < n; ++i) X[i] = xs[a + i];
+        orc_stats* st = j->stats ? &j->stats[j->woff[s] + w] : NULL;
+        window_apply(X, Y, n, med[w], mad[w], Dm, a, (uint32_t)s, j->seed, j->k[s], j->mode[s],
+                     -128, 127, st);
+        for (int32_t i = 0; i < n; ++i) ys[a + i] = (int8_t)Y[i];
+    }
+    free(med);
+    free(mad);
+    free(X);
+    free(Y);
+    free(sorted);
+}
+
+static void* mom_worker(void* arg)
+{
+    const mom_job* j = (const mom_job*)arg;
+    for (int32_t s = j->first; s < j->last; ++s) mom_stream(j, s);
+    return NULL;
+}
+
+int orc_mom_filter_i8(const int8_t* x, int8_t* y, int32_t n_streams, const int64_t* lengths,
+                      const int32_t* windows, const float* k, const int32_t* mode, int32_t mom_k,
+                      uint64_t seed, orc_stats* stats, int32_t n_threads)
+{
+    if (n_streams < 0 || mom_k < 1) return -1;
+    if (n_streams == 0) return 0;
+    int64_t* soff = (int64_t*)malloc((size_t)n_streams * sizeof(int64_t));
+    int64_t* woff = (int64_t*)malloc((size_t)n_streams * sizeof(int64_t));
+    int64_t total = orc_layout(n_streams, lengths, windows, soff, woff);
+    for (int32_t s = 0; s < n_streams && total >= 0; ++s)
+        if (mode[s] < ORC_ZERO || mode[s] > ORC_NOISE || !(k[s] >= 0.0f)) total = -1;
+    if (total < 0) {
+        free(soff);
+        free(woff);
+        return -1;
+    }
+    pthread_once(&g_q8_once, q8_init);
+    if (n_threads < 1) n_threads = 1;
+    if (n_threads > n_streams) n_threads = n_streams;
+    pthread_t* tid = (pthread_t*)malloc((size_t)n_threads * sizeof(pthread_t));
+    mom_job* jobs = (mom_job*)malloc((size_t)n_threads * sizeof(mom_job));
+    for (int32_t i = 0; i < n_threads; ++i) {
+        mom_job j = {x, y, n_streams, lengths, windows, k, mode, mom_k, seed, stats, soff, woff,
+                     (int32_t)((int64_t)n_streams * i / n_threads),
+                     (int32_t)((int64_t)n_streams * (i + 1) / n_threads)};
+        jobs[i] = j;
+        pthread_create(&tid[i], NULL, mom_worker, &jobs[i]);
+    }
+    for (int32_t i = 0; i < n_threads; ++i) pthread_join(tid[i], NULL);
+    free(tid);
+    free(jobs);
+    free(soff);
+    free(woff);
+    return 0;
 }

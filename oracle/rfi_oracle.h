@@ -11,7 +11,9 @@
  *   per non-overlapping window of one input's time series, the median M(x),
  *   the median absolute deviation D, the thresholds of Eq. (1)
  *   M(x) +/- n * (1.4826 * D), and the replacement of Eq. (2) for every
- *   sample outside them (by zero, by the threshold, or by digital noise).
+ *   sample outside them (by zero, by the threshold, or by digital noise);
+ *   and the median-of-MAD variant of Eq. (3), which puts the median of the
+ *   MADs of k successive windows in place of D.
  *
  * Readings where the paper is silent (each listed in the design notes):
  *   - lower median: rank r = floor((N-1)/2) of the sorted window;
@@ -25,7 +27,9 @@
  *     scaled by the robust sigma, indexed by a 12-bit field of a
  *     Philox4x64-10 block (Salmon et al., SC'11) keyed by (seed, stream):
  *     counter j >> 2 for absolute sample index j, word j & 3, top 12 bits;
- *   - a short final window is a window of its own.
+ *   - a short final window is a window of its own;
+ *   - median of MAD: the k windows are the current one and the k-1 before
+ *     it (causal, sliding), fewer at the start of a stream; lower median.
  */
 #ifndef RFI_ORACLE_H
 #define RFI_ORACLE_H
@@ -74,6 +78,18 @@ int orc_filter_i8(const int8_t* x, int8_t* y, int32_t n_streams, const int64_t* 
 int orc_filter_i16(const int16_t* x, int16_t* y, int32_t n_streams, const int64_t* lengths,
                    const int32_t* windows, const float* k, const int32_t* mode, uint64_t seed,
                    orc_stats* stats, int32_t n_threads);
+
+/* Median of MAD (Eq. (3)), int8.  Per stream: the lower median M(x) and
+ * MAD D of every window as above; for window w the threshold uses
+ * M_m(w) = lower median of the MADs of windows max(0, w-K+1) .. w
+ * (K = mom_k >= 1; fewer at the start of the stream) in place of D:
+ * t = k * (1.4826f * (float)M_m(w)), flag |x - M(x)| > t, replacement and
+ * noise scale as above with M_m(w).  Stats: median, the window's own MAD,
+ * n_flagged, t.  Streams are spread over n_threads threads.
+ * Returns 0, or -1 on an invalid argument. */
+int orc_mom_filter_i8(const int8_t* x, int8_t* y, int32_t n_streams, const int64_t* lengths,
+                      const int32_t* windows, const float* k, const int32_t* mode, int32_t mom_k,
+                      uint64_t seed, orc_stats* stats, int32_t n_threads);
 
 #ifdef __cplusplus
 }
