@@ -122,6 +122,21 @@ const char* rfi_status_string(int status);
 /* Version string of the library build. */
 const char* rfi_version(void);
 
+/* Median of MAD (Eq. (3)), int8.  Same buffers, layout, ownership,
+ * asynchrony and errors as rfi_mad_filter, plus mom_k >= 1 (else
+ * RFI_ERR_INVALID).  Each window's threshold uses, in place of its own MAD,
+ * the lower median of the MADs of the mom_k windows of its stream ending
+ * at it (fewer at the start of the stream):
+ *   t = k * (1.4826f * (float)M_m),  M_m = lowmed(D_{w-K+1} .. D_w);
+ * the centre stays the window's median, the noise scale is
+ * (int)(1.4826f * M_m * 256.0f).  stats_out receives the window's median,
+ * its own MAD, the flag count and t (it may be NULL).  Three passes over
+ * the batch (statistics, median of MADs, replacement): the input is read
+ * twice. */
+int rfi_mom_filter(const int8_t* x, int8_t* y, int32_t n_streams, const int64_t* lengths,
+                   const int32_t* windows, const float* k, const int32_t* mode, int32_t mom_k,
+                   uint64_t seed, rfi_window_stats* stats_out, void* stream);
+
 /* ------------------------------------------------------------------ */
 /* Explicit plans: a work table for one argument signature, reusable   */
 /* across calls, with a selectable launch schedule and HIP-graph       */

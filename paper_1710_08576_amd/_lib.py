@@ -52,6 +52,7 @@ PP = ctypes.POINTER(ctypes.c_void_p)
 _SIGS = {
     "rfi_mad_filter": (ctypes.c_int, [P, P, I32, P, P, P, P, U64, P, P]),
     "rfi_mad_filter_i16": (ctypes.c_int, [P, P, I32, P, P, P, P, U64, P, P]),
+    "rfi_mom_filter": (ctypes.c_int, [P, P, I32, P, P, P, P, I32, U64, P, P]),
     "rfi_layout": (ctypes.c_int64, [I32, P, P, P, P, P]),
     "rfi_validate": (ctypes.c_int, [I32, P, P, I32, P, P, P, P, P]),
     "rfi_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -188,6 +189,26 @@ def mad_filter(x, lengths, windows, k, mode, seed: int = 0, y=None, stats=True, 
     rc = f(_tptr(x), _tptr(y), n, _ptr(L), _ptr(W), _ptr(K), _ptr(M), seed, _tptr(st),
            _stream_handle(stream))
     _check(rc, "rfi_mad_filter")
+    return y, (st[:nw] if st is not None else None)
+
+
+def mom_filter(x, lengths, windows, k, mode, mom_k: int, seed: int = 0, y=None, stats=True,
+               stream=None):
+    """Median-of-MAD filter (Eq. (3)) of packed int8 streams; returns (y, stats)
+    like mad_filter."""
+    import torch
+    n = len(lengths)
+    L = np.ascontiguousarray(lengths, dtype=np.int64)
+    W, K, M = _arr(windows, np.int32, n), _arr(k, np.float32, n), _arr(mode, np.int32, n)
+    _, _, nw, _ = layout(L, W)
+    if x.dtype != torch.int8:
+        raise TypeError("x must be int8")
+    if y is None:
+        y = torch.empty_like(x)
+    st = torch.empty((max(nw, 1), 4), dtype=torch.int32, device=x.device) if stats else None
+    rc = load().rfi_mom_filter(_tptr(x), _tptr(y), n, _ptr(L), _ptr(W), _ptr(K), _ptr(M), int(mom_k),
+                               seed, _tptr(st), _stream_handle(stream))
+    _check(rc, "rfi_mom_filter")
     return y, (st[:nw] if st is not None else None)
 
 

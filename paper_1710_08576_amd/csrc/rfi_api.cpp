@@ -312,7 +312,9 @@ int plan_build(int elem, int32_t n, const int64_t* L, const int32_t* W, const fl
     const int ncls = elem == 1 ? kI8Classes : kI16Classes;
     // Item order: generic items, then the tiles of class 0, 1, ...; within a
     // class by mode, then stream, then position.
-    std::vector<std::vector<Item>> groups((ncls + 1) * 3);
+    // (modes 0..2 and the internal statistics-only mode)
+    constexpr int kModes = kModeStats + 1;
+    std::vector<std::vector<Item>> groups((ncls + 1) * kModes);
     int64_t soff = 0, woff = 0;
     p->hdesc.resize(n);
     for (int s = 0; s < n; ++s) {
@@ -335,7 +337,7 @@ int plan_build(int elem, int32_t n, const int64_t* L, const int32_t* W, const fl
         int64_t first_generic = 0;
         if (cls >= 0) {
             const int64_t nt = L[s] / tile_samples;
-            auto& grp = groups[(cls + 1) * 3 + M[s]];
+            auto& grp = groups[(cls + 1) * kModes + M[s]];
             for (int64_t t = 0; t < nt; ++t) grp.push_back(Item{s, kItemTile, t * tile_samples});
             first_generic = nt * (tile_samples / W[s]);
             p->n_tiles += nt;
@@ -347,11 +349,11 @@ int plan_build(int elem, int32_t n, const int64_t* L, const int32_t* W, const fl
         woff += nw;
     }
     for (auto& g : groups) p->hitems.insert(p->hitems.end(), g.begin(), g.end());
-    for (int m = 0; m < 3; ++m) {
+    for (int m = 0; m < 3; ++m) {  // the statistics-only mode has no fused launch
         for (const Item& it : groups[0])
             if (M[it.stream] == m) p->hitems_fused.push_back(it);
         for (int c = 0; c < ncls; ++c) {
-            const auto& g = groups[(c + 1) * 3 + m];
+            const auto& g = groups[(c + 1) * kModes + m];
             p->hitems_fused.insert(p->hitems_fused.end(), g.begin(), g.end());
         }
     }
@@ -366,11 +368,13 @@ int plan_build(int elem, int32_t n, const int64_t* L, const int32_t* W, const fl
         if (e != hipSuccess) return e == hipErrorOutOfMemory ? RFI_ERR_NOMEM : hip_fail(e);
         e = hipMemcpy(p->ditems, p->hitems.data(), sizeof(Item) * p->hitems.size(), hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(e);
-        e = hipMalloc(&p->ditems_fused, sizeof(Item) * p->hitems_fused.size());
-        if (e != hipSuccess) return e == hipErrorOutOfMemory ? RFI_ERR_NOMEM : hip_fail(e);
-        e = hipMemcpy(p->ditems_fused, p->hitems_fused.data(), sizeof(Item) * p->hitems_fused.size(),
-                      hipMemcpyHostToDevice);
-        if (e != hipSuccess) return hip_fail(e);
+        if (!p->hitems_fused.empty()) {
+            e = hipMalloc(&p->ditems_fused, sizeof(Item) * p->hitems_fused.size());
+            if (e != hipSuccess) return e == hipErrorOutOfMemory ? RFI_ERR_NOMEM : hip_fail(e);
+            e = hipMemcpy(p->ditems_fused, p->hitems_fused.data(), sizeof(Item) * p->hitems_fused.size(),
+                          hipMemcpyHostToDevice);
+            if (e != hipSuccess) return hip_fail(e);
+        }
     }
     build_launches(p.get());
     *out = p.release();
@@ -791,6 +795,7 @@ int rfi_mad_filter_i16(const int16_t* x, int16_t* y, int32_t n_streams, const in
 
 int rfi_shutdown(void)
 {
+    rfi::mom_shutdown();
     std::lock_guard<std::mutex> g(g_cache_mu);
     for (auto& kv : g_cache) rfi::plan_free(kv.second);
     g_cache.clear();

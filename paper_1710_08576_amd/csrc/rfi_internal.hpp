@@ -81,6 +81,11 @@ constexpr int kI8Classes = 6;
 inline __host__ __device__ int i16_tile_class(int32_t w) { return w == 8192 ? 0 : -1; }
 constexpr int kI16Classes = 1;
 
+// Internal mode: compute window statistics only (median, MAD, and the flag
+// count and threshold of the window's own MAD); write no samples.  Used by
+// the median-of-MAD path's first pass.
+constexpr int32_t kModeStats = 3;
+
 // Kernel launch requests issued by the host runtime.
 struct LaunchArgs {
     const StreamDesc* streams;
@@ -122,6 +127,35 @@ hipError_t launch_i8_fused(int modes, const LaunchArgs& a, int grid, hipStream_t
 hipError_t launch_i16_tiles(int cls, const LaunchArgs& a, int grid, hipStream_t s);
 hipError_t launch_i16_generic(const LaunchArgs& a, int grid, hipStream_t s);
 hipError_t launch_i16_fused(const LaunchArgs& a, int grid, hipStream_t s);
+
+// Median of MAD (int8).  Windows of all streams are numbered globally in
+// the packed stats order; mad[g] is window g's own MAD, dm[g] receives the
+// lower median of the MADs of its stream's windows max(0, w-K+1) .. w.
+struct MomStream {
+    int64_t woff;   // first global window index of the stream
+    int64_t nw;     // windows of the stream
+    int64_t hoff;   // first row of the stream's block-count table
+};
+constexpr int kMomBlock = 64;  // windows per row of the block-count table
+// hcnt[(hoff + b) * 256 + v] = #{j < 64 b : mad_j <= v} of the stream.
+hipError_t launch_mom_counts(const MomStream* streams, int n_streams, const uint8_t* mad,
+                             uint32_t* hcnt, hipStream_t s);
+hipError_t launch_mom_select(const MomStream* streams, int n_streams, int64_t total_windows,
+                             int32_t mom_k, const uint8_t* mad, const uint32_t* hcnt, int32_t* dm,
+                             hipStream_t s);
+// Replacement pass: items of up to 256 windows (<= 16 KiB) of one stream;
+// window params from stats (median) and dm; rewrites n_flagged and threshold.
+struct MomItem {
+    int32_t stream;
+    int32_t n_windows;
+    int64_t first_window;  // within the stream
+};
+hipError_t launch_mom_apply(const LaunchArgs& a, const MomItem* items, int64_t n_items,
+                            const int32_t* dm, const int64_t* stream_woff, rfi_window_stats* stats,
+                            hipStream_t s);
+// Copies the MAD of every window out of the stats array (int8 MADs fit a byte).
+hipError_t launch_mom_gather(const rfi_window_stats* stats, int64_t total_windows, uint8_t* mad,
+                             hipStream_t s);
 
 // Serving carry update: copies logical elements [from, from + count) of the
 // concatenation (head[0 .. head_len), body[...]) to dst.  Addresses are

@@ -527,7 +527,7 @@ __device__ __forceinline__ TileStats i8_tile(const StreamView& d, int64_t first,
             __syncthreads();
             p = sm.prm[wl];
         }
-        i8_replace<W, NS, MODE>(d, first, seed, sm, v, [&](int) { return p; });
+        if constexpr (MODE != kModeStats) i8_replace<W, NS, MODE>(d, first, seed, sm, v, [&](int) { return p; });
     } else {
         // Several windows per wave: one 256-bin histogram of x + 128 per
         // window.  W = 512 takes its eight windows per wave in two rounds
@@ -603,15 +603,18 @@ __device__ __forceinline__ TileStats i8_tile(const StreamView& d, int64_t first,
             }
         }
         wave_sync();
-        i8_replace<W, NS, MODE>(d, first, seed, sm, v, [&](int i) {
-            return sm.prm[(wbase + i * 1024 + lane * 16) / W];
-        });
+        if constexpr (MODE != kModeStats)
+            i8_replace<W, NS, MODE>(d, first, seed, sm, v, [&](int i) {
+                return sm.prm[(wbase + i * 1024 + lane * 16) / W];
+            });
     }
 
-    uint8_t* yt = static_cast<uint8_t*>(d.y) + first + wbase + lane * 16;
+    if constexpr (MODE != kModeStats) {
+        uint8_t* yt = static_cast<uint8_t*>(d.y) + first + wbase + lane * 16;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-        gstore16_nt(yt + i * 1024, make_uint4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]));
+        for (int i = 0; i < 4; ++i)
+            gstore16_nt(yt + i * 1024, make_uint4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]));
+    }
     return ts;
 }
 
@@ -621,7 +624,9 @@ __device__ __forceinline__ TileStats i8_tile_any(const StreamView& d, int64_t fi
                                                  I8TileSmem<W, NS>& sm, uint32_t (&v)[16])
 {
     static_assert(!(MODES & 4) || NS, "noise needs its LDS scratch");
-    if constexpr (MODES == 1) {
+    if constexpr (MODES == (1 << kModeStats)) {
+        return i8_tile<W, false, kModeStats>(d, first, seed, sm, v);
+    } else if constexpr (MODES == 1) {
         return i8_tile<W, NS, RFI_MODE_ZERO>(d, first, seed, sm, v);
     } else if constexpr (MODES == 2) {
         return i8_tile<W, NS, RFI_MODE_CLIP>(d, first, seed, sm, v);
@@ -690,6 +695,7 @@ __device__ void i8_generic(const StreamView& d, int64_t w, uint64_t seed, Generi
         }
     }
     __syncthreads();
+    if (d.mode == kModeStats) return;
     const WinParams p = sm.prm;
     for (int i = tid; i < n; i += kBlock) {
         const int x = load_logical<int8_t>(d, a + i);
@@ -1252,6 +1258,164 @@ __global__ __launch_bounds__(kBlock) void k_i16_fused(LaunchArgs a)
     });
 }
 
+// ---------------------------------------------------------------------------
+// Median of MAD (Eq. (3)), int8: the MADs of the first pass are gathered,
+// counted per stream in blocks of 64 windows, and each window's lower
+// median of the MADs of its K-window history is found by a binary search
+// over the 256 possible MAD values on those counts; a last pass applies
+// Eqs. (1)-(2) with it.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_mom_gather(const rfi_window_stats* __restrict__ stats,
+                                                       int64_t total, uint8_t* __restrict__ mad)
+{
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g < total) mad[g] = (uint8_t)stats[g].mad;
+}
+
+// Thread v of stream blockIdx.x: row b of the stream's table holds
+// #{j < 64 b : mad_j <= v}, for b = 0 .. ceil(nw / 64).
+__global__ __launch_bounds__(256) void k_mom_counts(const MomStream* __restrict__ streams,
+                                                    const uint8_t* __restrict__ mad,
+                                                    uint32_t* __restrict__ hcnt)
+{
+    const MomStream st = streams[blockIdx.x];
+    const uint32_t v = threadIdx.x;
+    const uint8_t* m = mad + st.woff;
+    uint32_t* row = hcnt + st.hoff * 256 + v;
+    uint32_t run = 0;
+    for (int64_t b = 0;; ++b) {
+        row[b * 256] = run;
+        const int64_t j0 = b * kMomBlock;
+        if (j0 >= st.nw) break;
+        const int64_t j1 = min(j0 + kMomBlock, st.nw);
+        for (int64_t j = j0; j < j1; ++j) run += m[j] <= v ? 1u : 0u;
+    }
+}
+
+// #{j < p : mad_j <= v} from the block table and the partial block.
+__device__ __forceinline__ uint32_t mom_prefix(const uint8_t* m, const uint32_t* h, int64_t p, int v)
+{
+    const int64_t b = p / kMomBlock;
+    uint32_t c = h[b * 256 + v];
+    for (int64_t j = b * kMomBlock; j < p; ++j) c += m[j] <= v ? 1u : 0u;
+    return c;
+}
+
+__global__ __launch_bounds__(kBlock) void k_mom_select(const MomStream* __restrict__ streams, int n_streams,
+                                                       int64_t total, int32_t K,
+                                                       const uint8_t* __restrict__ mad,
+                                                       const uint32_t* __restrict__ hcnt,
+                                                       int32_t* __restrict__ dm)
+{
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= total) return;
+    int lo_s = 0, hi_s = n_streams - 1;  // last stream with woff <= g
+    while (lo_s < hi_s) {
+        const int mid = (lo_s + hi_s + 1) / 2;
+        if (streams[mid].woff <= g) lo_s = mid;
+        else hi_s = mid - 1;
+    }
+    const MomStream st = streams[lo_s];
+    const int64_t w = g - st.woff;
+    const int64_t a = w + 1 > K ? w + 1 - K : 0, b = w + 1;
+    const uint32_t need = (uint32_t)((b - a - 1) / 2 + 1);
+    const uint8_t* m = mad + st.woff;
+    const uint32_t* h = hcnt + st.hoff * 256;
+    int lo = 0, hi = 255;  // smallest v with #{a <= j < b : mad_j <= v} >= need
+    while (lo < hi) {
+        const int mid = (lo + hi) / 2;
+        if (mom_prefix(m, h, b, mid) - mom_prefix(m, h, a, mid) >= need) hi = mid;
+        else lo = mid + 1;
+    }
+    dm[g] = lo;
+}
+
+struct MomSmem {
+    WinParams prm[256];
+    float thr[256];
+    uint32_t flagged[256];
+};
+
+// One item: up to 256 whole windows (<= 16 KiB, or one window) of a stream.
+__global__ __launch_bounds__(kBlock) void k_mom_apply(LaunchArgs a, const MomItem* __restrict__ items,
+                                                      const int32_t* __restrict__ dm,
+                                                      const int64_t* __restrict__ stream_woff,
+                                                      rfi_window_stats* __restrict__ stats)
+{
+    __shared__ MomSmem sm;
+    const MomItem it = items[blockIdx.x];
+    const StreamView d = resolve(a.streams[it.stream], a);
+    const int tid = (int)threadIdx.x;
+    const int W = d.window;
+    const int64_t g0 = stream_woff[it.stream] + it.first_window;
+    if (tid < it.n_windows) {
+        const int m = stats[g0 + tid].median;
+        float sig;
+        const float t = threshold_of(dm[g0 + tid], d.k, sig);
+        const int T = (int)floorf(t);
+        WinParams p;
+        p.m = m;
+        p.lo = max(m - T, -128);
+        p.hi = min(m + T, 127);
+        p.sq8 = (int)__fmul_rn(sig, 256.0f);
+        sm.prm[tid] = p;
+        sm.thr[tid] = t;
+        sm.flagged[tid] = 0;
+    }
+    __syncthreads();
+    const int64_t s0 = it.first_window * (int64_t)W;
+    const int64_t s1 = min((it.first_window + it.n_windows) * (int64_t)W, d.length);
+    const int8_t* x = static_cast<const int8_t*>(d.x);
+    int8_t* y = static_cast<int8_t*>(d.y);
+    for (int64_t c = s0 - (s0 & 15) + 16 * (int64_t)tid; c < s1; c += 16 * kBlock) {
+        const int64_t lw = c / W - it.first_window;  // window of the chunk's first sample
+        if (c >= s0 && c + 16 <= s1 && (c + 15) / W == c / W) {
+            const WinParams p = sm.prm[lw];
+            const uint4 xv = gload16(x + c);
+            const uint32_t lo_u = rep_i16((p.lo + 128) * 256), hi_u = rep_i16((p.hi + 128) * 256);
+            uint32_t w4[4] = {xv.x, xv.y, xv.z, xv.w};
+            uint32_t nf = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t f = flag_sel_i8x4(w4[q], lo_u, hi_u);  // byte_perm selector
+                const uint32_t clipped = clamp_i8x4(w4[q], rep_i16(p.lo * 256), rep_i16(p.hi * 256));
+                const uint32_t diff = clipped ^ w4[q];
+                if (diff != 0) {
+                    nf += __popc(nonzero_byte_mask(diff)) / 8;
+                    if (d.mode == RFI_MODE_CLIP) w4[q] = clipped;
+                    else if (d.mode == RFI_MODE_ZERO) w4[q] = byte_perm(0u, w4[q], f);
+                    else w4[q] = byte_perm(noise_quad_i8((uint64_t)(d.abs_base + c + 4 * q), a.seed, d.key,
+                                                         p.m, p.sq8),
+                                           w4[q], f);
+                }
+            }
+            gstore16(y + c, make_uint4(w4[0], w4[1], w4[2], w4[3]));
+            if (nf) atomicAdd(&sm.flagged[lw], nf);
+        } else {
+            for (int i = 0; i < 16; ++i) {
+                const int64_t j = c + i;
+                if (j < s0 || j >= s1) continue;
+                const int64_t wl = j / W - it.first_window;
+                const WinParams p = sm.prm[wl];
+                const int xv = gload(x + j);
+                int yv = xv;
+                if (xv < p.lo || xv > p.hi) {
+                    atomicAdd(&sm.flagged[wl], 1u);
+                    if (d.mode == RFI_MODE_ZERO) yv = 0;
+                    else if (d.mode == RFI_MODE_CLIP) yv = min(max(xv, p.lo), p.hi);
+                    else yv = noise_sample(d.abs_base + j, a.seed, d.key, p.m, p.sq8, -128, 127);
+                }
+                gstore(y + j, (int8_t)yv);
+            }
+        }
+    }
+    __syncthreads();
+    if (tid < it.n_windows) {
+        stats[g0 + tid].n_flagged = sm.flagged[tid];
+        stats[g0 + tid].threshold = sm.thr[tid];
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_carry(const CarryItem* __restrict__ items)
 {
     const CarryItem c = items[blockIdx.x];
@@ -1326,6 +1490,7 @@ static void (*i8_tile_kernel_p(int cls, int modes, int tpw))(LaunchArgs)
         case 2: return i8_tile_kernel_m<2, PERSIST>(cls, tpw);
         case 3: return i8_tile_kernel_m<3, PERSIST>(cls, tpw);
         case 4: return i8_tile_kernel_m<4, PERSIST>(cls, tpw);
+        case 1 << kModeStats: return i8_tile_kernel_m<1 << kModeStats, PERSIST>(cls, tpw);
         default: return i8_tile_kernel_m<7, PERSIST>(cls, tpw);
     }
 }
@@ -1379,6 +1544,41 @@ hipError_t launch_i16_fused(const LaunchArgs& a, int grid, hipStream_t s)
     return launch(RFI_PICK(k_i16_fused, a, grid), a, grid, s);
 }
 #undef RFI_PICK
+
+hipError_t launch_mom_gather(const rfi_window_stats* stats, int64_t total, uint8_t* mad, hipStream_t s)
+{
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mom_gather, dim3((unsigned)((total + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       stats, total, mad);
+    return hipGetLastError();
+}
+
+hipError_t launch_mom_counts(const MomStream* streams, int n_streams, const uint8_t* mad, uint32_t* hcnt,
+                             hipStream_t s)
+{
+    if (n_streams <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mom_counts, dim3(n_streams), dim3(256), 0, s, streams, mad, hcnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_mom_select(const MomStream* streams, int n_streams, int64_t total, int32_t K,
+                             const uint8_t* mad, const uint32_t* hcnt, int32_t* dm, hipStream_t s)
+{
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mom_select, dim3((unsigned)((total + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       streams, n_streams, total, K, mad, hcnt, dm);
+    return hipGetLastError();
+}
+
+hipError_t launch_mom_apply(const LaunchArgs& a, const MomItem* items, int64_t n_items, const int32_t* dm,
+                            const int64_t* stream_woff, rfi_window_stats* stats, hipStream_t s)
+{
+    if (n_items <= 0) return hipSuccess;
+    if (n_items > (1 << 30)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mom_apply, dim3((unsigned)n_items), dim3(kBlock), 0, s, a, items, dm, stream_woff,
+                       stats);
+    return hipGetLastError();
+}
 
 hipError_t launch_carry(const CarryItem* items, int n_items, hipStream_t s)
 {

@@ -1,0 +1,123 @@
+"""Median-of-MAD path (Eq. (3)) on the device against the oracle, bit-exact."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1710_08576_amd as rfi
+from paper_1710_08576_amd import synth
+
+pytestmark = pytest.mark.gpu
+SENT = 0x5A
+
+
+def _run(x_np, L, W, K, M, mom_k, seed, dev, inplace=False, stats=True):
+    xd = torch.from_numpy(x_np.copy()).to(dev)
+    yd = xd if inplace else torch.full_like(xd, SENT)
+    y, st = rfi.mom_filter(xd, L, W, K, M, mom_k, seed=seed, y=yd, stats=stats)
+    torch.cuda.synchronize()
+    return y.cpu().numpy(), (rfi.stats_numpy(st) if st is not None else None)
+
+
+def _check(x_np, L, W, K, M, mom_k, seed, y, st, padding=True):
+    yo, sto = oracle.mom_filter_batch(x_np, L, W, K, M, mom_k, seed=seed)
+    so, _, _, _ = rfi.layout(L, W)
+    for s, (o, n) in enumerate(zip(so, L)):
+        a, b = y[o:o + n], yo[o:o + n]
+        if not np.array_equal(a, b):
+            bad = np.nonzero(a != b)[0]
+            raise AssertionError(f"stream {s} W={W[s]} mode={M[s]}: {len(bad)} differ, first {bad[0]}: "
+                                 f"gpu {a[bad[0]]} oracle {b[bad[0]]}")
+        if padding:
+            pad = y[o + n:o + synth.align_up(n)].view(np.uint8)
+            assert np.all(pad == SENT), f"padding of stream {s} written"
+    if st is not None:
+        if not np.array_equal(st, sto):
+            bad = np.nonzero(st != sto)[0]
+            raise AssertionError(f"stats differ at window {bad[0]}: {st[bad[0]]} vs {sto[bad[0]]}")
+
+
+def _batch(specs, seed):
+    x = synth.gen_packed(specs, seed, 31).numpy()
+    return x, [s.length for s in specs], [s.window for s in specs], [s.k for s in specs], \
+        [s.mode for s in specs]
+
+
+@pytest.mark.parametrize("mom_k", [1, 2, 7, 64, 4096])
+def test_mixed_batch(gpu, mom_k):
+    specs = []
+    for i, (W, L) in enumerate([(4096, 4096 * 37 + 100), (512, 512 * 150), (1000, 61_111),
+                                (16384, 16384 * 5 + 3), (2048, 2048 * 70), (777, 50_000),
+                                (8192, 8192 * 9), (1, 500), (13, 4_000), (1024, 1024 * 80 + 1)]):
+        sig = 4.0 + 3.0 * i
+        specs.append(synth.StreamSpec(L, W, [2.5, 3.0, 3.5][i % 3], i % 3, sig, 0.01, 8, 2000))
+    x, L, W, K, M = _batch(specs, 40 + mom_k)
+    y, st = _run(x, L, W, K, M, mom_k, 5, gpu)
+    _check(x, L, W, K, M, mom_k, 5, y, st)
+
+
+def test_k1_equals_plain_filter(gpu):
+    specs = [synth.StreamSpec(4096 * 40, 4096, 3.0, m, 10.0, 0.01, 8, 500) for m in (0, 1, 2)]
+    x, L, W, K, M = _batch(specs, 3)
+    y1, s1 = _run(x, L, W, K, M, 1, 9, gpu)
+    xd = torch.from_numpy(x.copy()).to(gpu)
+    y0, s0 = rfi.mad_filter(xd, L, W, K, M, seed=9, y=torch.full_like(xd, SENT))
+    so = rfi.layout(L, W)[0]
+    y0 = y0.cpu().numpy()
+    for o, n in zip(so, L):
+        assert np.array_equal(y1[o:o + n], y0[o:o + n])
+    assert np.array_equal(s1, rfi.stats_numpy(s0))
+
+
+def test_inplace_and_no_stats(gpu):
+    specs = [synth.StreamSpec(100_000, 2048, 3.0, 2, 15.0, 0.02, 8, 3000),
+             synth.StreamSpec(70_000, 700, 3.0, 0, 8.0, 0.01, 8, 900)]
+    x, L, W, K, M = _batch(specs, 8)
+    y, _ = _run(x, L, W, K, M, 16, 2, gpu, inplace=True, stats=False)
+    _check(x, L, W, K, M, 16, 2, y, None, padding=False)
+
+
+def test_long_bursts_caught(gpu):
+    """A burst longer than half a window inflates that window's MAD so the
+    plain filter misses it; the median of MADs keeps the threshold low."""
+    W = 4096
+    L = W * 64
+    g = np.random.default_rng(1)
+    x = np.clip(np.rint(g.normal(0, 8, L)), -128, 127)
+    b0 = W * 40 + 100
+    x[b0:b0 + 3000] = np.clip(x[b0:b0 + 3000] + g.choice([-80, 80], 3000), -128, 127)
+    x = x.astype(np.int8)
+    y_mad, st_mad = _run(x, [L], [W], [3.0], [0], 1, 0, gpu)
+    y_mom, st_mom = _run(x, [L], [W], [3.0], [0], 32, 0, gpu)
+    _check(x, [L], [W], [3.0], [0], 32, 0, y_mom, st_mom)
+    assert st_mom[40]["n_flagged"] > 2500 > st_mad[40]["n_flagged"]
+
+
+def test_full_size_sampled(gpu):
+    """60 x 2^24, W 4096, K 4096 (the paper's median-of-MAD setting): two
+    streams checked against the oracle, the rest by properties."""
+    specs = synth.plain_scale(60, 1 << 24, 4096, rfi.CLIP)
+    L = [s.length for s in specs]
+    xd = synth.gen_packed(specs, 0, 77, device=gpu)
+    y, st = rfi.mom_filter(xd, L, [4096] * 60, [3.0] * 60, [1] * 60, 4096, seed=3)
+    torch.cuda.synchronize()
+    so = rfi.layout(L, [4096] * 60)[0]
+    stn = rfi.stats_numpy(st)
+    for s in (0, 37):
+        xs = xd[so[s]:so[s] + L[s]].cpu().numpy()
+        # stream s sits behind s empty streams, so its key is s
+        Ls = [0] * s + [L[s]]
+        yo, sto = oracle.mom_filter_batch(xs, Ls, [4096] * (s + 1), 3.0, 1, 4096, seed=3)
+        assert np.array_equal(y[so[s]:so[s] + L[s]].cpu().numpy(), yo[:L[s]])
+        assert np.array_equal(stn[s * 4096:(s + 1) * 4096], sto)
+    # CLIP never widens a sample's deviation beyond its window's threshold
+    assert np.all(stn["threshold"] >= 0)
+
+
+def test_arg_errors(gpu):
+    xd = torch.zeros(4096, dtype=torch.int8, device=gpu)
+    with pytest.raises(rfi.RfiError) as e:
+        rfi.mom_filter(xd, [4096], [1024], [3.0], [1], 0)
+    assert e.value.status == -1
+    with pytest.raises(rfi.RfiError):
+        rfi.mom_filter(xd, [4096], [0], [3.0], [1], 4)
