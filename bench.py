@@ -79,6 +79,7 @@ def main():
     ap.add_argument("--no-batching", action="store_true")
     ap.add_argument("--no-int16", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-mom", action="store_true")
     ap.add_argument("--serve-blocks", type=int, default=10000,
                     help="blocks per stream in the real-time serving replay")
     ap.add_argument("--with-copy", action="store_true",
@@ -213,6 +214,8 @@ def main():
         out["batching"] = bench_batching(args, dev)
     if not args.no_int16:
         out["int16"] = bench_int16(args, dev)
+    if not args.no_mom:
+        out["median_of_mad"] = bench_mom(args, dev, x, y, L)
     if not args.no_serving:
         del x, y
         torch.cuda.empty_cache()
@@ -344,6 +347,39 @@ def bench_int16(args, dev):
     return {"workload": "60 x 2^23 int16, window 8192, k 3, noise", "ms": round(ms, 4),
             "gsamples_s": round(n / ms / 1e6, 1), "gb_s": round(ab / ms / 1e6, 1),
             "roofline_frac": round(ab / ms / 1e6 / HBM_PEAK_GBS, 4)}
+
+
+def bench_mom(args, dev, x, y, L):
+    """Median of MAD (K = 4096 windows of 4096, the paper's setting) on the
+    plain-scale batch: statistics pass, median of MADs, replacement pass."""
+    import numpy as np
+    import torch
+
+    import paper_1710_08576_amd as rfi
+    from paper_1710_08576_amd import _lib
+    n, ns = sum(L), len(L)
+    nw = rfi.layout(L, [4096] * ns)[2]
+    st = torch.empty((nw, 4), dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    Ls = np.ascontiguousarray(L, dtype=np.int64)
+    Ws = np.full(ns, 4096, dtype=np.int32)
+    Ks = np.full(ns, 3.0, dtype=np.float32)
+    res = {"workload": "plain-scale 60 x 2^24 int8, W 4096, median of the MADs of 4096 windows, k 3",
+           "algorithmic_bytes": "3 B/sample (x read twice, y written once) + 16 B/window"}
+    ab = 3 * n + 16 * nw
+    for name, m in (("zero", 0), ("clip", 1), ("noise", 2)):
+        Ms = np.full(ns, m, dtype=np.int32)
+
+        def fn():
+            _lib._check(_lib.load().rfi_mom_filter(
+                _lib._tptr(x), _lib._tptr(y), ns, _lib._ptr(Ls), _lib._ptr(Ws), _lib._ptr(Ks),
+                _lib._ptr(Ms), 4096, 1, _lib._tptr(st), _lib._stream_handle(stream)), "rfi_mom_filter")
+        for _ in range(3):
+            fn()
+        ms = _time_events(fn, max(10, args.steps // 5), stream)
+        res[name] = {"ms": round(ms, 4), "gsamples_s": round(n / ms / 1e6, 1),
+                     "gb_s": round(ab / ms / 1e6, 1), "roofline_frac": round(ab / ms / 1e6 / HBM_PEAK_GBS, 4)}
+    return res
 
 
 DEADLINE_NS = (1 << 20) / 800e6 * 1e9  # one 2^20-sample block at 800 Msample/s

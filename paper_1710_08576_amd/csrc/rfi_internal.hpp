@@ -138,8 +138,9 @@ struct MomStream {
 };
 constexpr int kMomBlock = 64;  // windows per row of the block-count table
 // hcnt[(hoff + b) * 256 + v] = #{j < 64 b : mad_j <= v} of the stream.
-hipError_t launch_mom_counts(const MomStream* streams, int n_streams, const uint8_t* mad,
-                             uint32_t* hcnt, hipStream_t s);
+// max_blocks: the largest ceil(nw / 64) over the streams.
+hipError_t launch_mom_counts(const MomStream* streams, int n_streams, int64_t max_blocks,
+                             const uint8_t* mad, uint32_t* hcnt, hipStream_t s);
 hipError_t launch_mom_select(const MomStream* streams, int n_streams, int64_t total_windows,
                              int32_t mom_k, const uint8_t* mad, const uint32_t* hcnt, int32_t* dm,
                              hipStream_t s);

@@ -1272,23 +1272,38 @@ __global__ __launch_bounds__(kBlock) void k_mom_gather(const rfi_window_stats* _
     if (g < total) mad[g] = (uint8_t)stats[g].mad;
 }
 
-// Thread v of stream blockIdx.x: row b of the stream's table holds
-// #{j < 64 b : mad_j <= v}, for b = 0 .. ceil(nw / 64).
+// Two steps build row b of a stream's table, #{j < 64 b : mad_j <= v} for
+// b = 0 .. ceil(nw / 64): per block of 64 windows (blockIdx.x = block b of
+// stream blockIdx.y, thread v) the block's own count goes to row b + 1, then
+// one workgroup per stream turns the rows into running sums.
+__global__ __launch_bounds__(256) void k_mom_block_counts(const MomStream* __restrict__ streams,
+                                                          const uint8_t* __restrict__ mad,
+                                                          uint32_t* __restrict__ hcnt)
+{
+    const MomStream st = streams[blockIdx.y];
+    const int64_t j0 = (int64_t)blockIdx.x * kMomBlock;
+    if (j0 >= st.nw) return;
+    __shared__ uint8_t m[kMomBlock];
+    const int64_t j1 = min(j0 + kMomBlock, st.nw);
+    if ((int64_t)threadIdx.x < j1 - j0) m[threadIdx.x] = mad[st.woff + j0 + threadIdx.x];
+    __syncthreads();
+    const uint32_t v = threadIdx.x;
+    uint32_t c = 0;
+    for (int j = 0; j < (int)(j1 - j0); ++j) c += m[j] <= v ? 1u : 0u;
+    hcnt[(st.hoff + blockIdx.x + 1) * 256 + v] = c;
+}
+
 __global__ __launch_bounds__(256) void k_mom_counts(const MomStream* __restrict__ streams,
-                                                    const uint8_t* __restrict__ mad,
                                                     uint32_t* __restrict__ hcnt)
 {
     const MomStream st = streams[blockIdx.x];
-    const uint32_t v = threadIdx.x;
-    const uint8_t* m = mad + st.woff;
-    uint32_t* row = hcnt + st.hoff * 256 + v;
+    uint32_t* row = hcnt + st.hoff * 256 + threadIdx.x;
+    const int64_t nb = (st.nw + kMomBlock - 1) / kMomBlock;
     uint32_t run = 0;
-    for (int64_t b = 0;; ++b) {
+    row[0] = 0;
+    for (int64_t b = 1; b <= nb; ++b) {
+        run += row[b * 256];
         row[b * 256] = run;
-        const int64_t j0 = b * kMomBlock;
-        if (j0 >= st.nw) break;
-        const int64_t j1 = min(j0 + kMomBlock, st.nw);
-        for (int64_t j = j0; j < j1; ++j) run += m[j] <= v ? 1u : 0u;
     }
 }
 
@@ -1334,17 +1349,23 @@ struct MomSmem {
     WinParams prm[256];
     float thr[256];
     uint32_t flagged[256];
+    uint32_t noise_counts[4];
+    __align__(16) uint32_t noise_list[256];
+    __align__(16) uint32_t noise_data[256];
+    __device__ NoiseScratch noise()
+    {
+        return NoiseScratch{noise_counts, noise_list, reinterpret_cast<uint4*>(noise_data)};
+    }
 };
 
-// One item: up to 256 whole windows (<= 16 KiB, or one window) of a stream.
-__global__ __launch_bounds__(kBlock) void k_mom_apply(LaunchArgs a, const MomItem* __restrict__ items,
-                                                      const int32_t* __restrict__ dm,
-                                                      const int64_t* __restrict__ stream_woff,
-                                                      rfi_window_stats* __restrict__ stats)
+// One item: up to 256 whole windows (<= 16 KiB, or one window) of a stream,
+// compiled per mode (the stream's mode is uniform over the workgroup).
+template <int MODE>
+__device__ __forceinline__ void mom_apply_item(const LaunchArgs& a, const MomItem& it, const StreamView& d,
+                                               const int32_t* __restrict__ dm,
+                                               const int64_t* __restrict__ stream_woff,
+                                               rfi_window_stats* __restrict__ stats, MomSmem& sm)
 {
-    __shared__ MomSmem sm;
-    const MomItem it = items[blockIdx.x];
-    const StreamView d = resolve(a.streams[it.stream], a);
     const int tid = (int)threadIdx.x;
     const int W = d.window;
     const int64_t g0 = stream_woff[it.stream] + it.first_window;
@@ -1367,46 +1388,73 @@ __global__ __launch_bounds__(kBlock) void k_mom_apply(LaunchArgs a, const MomIte
     const int64_t s1 = min((it.first_window + it.n_windows) * (int64_t)W, d.length);
     const int8_t* x = static_cast<const int8_t*>(d.x);
     int8_t* y = static_cast<int8_t*>(d.y);
-    for (int64_t c = s0 - (s0 & 15) + 16 * (int64_t)tid; c < s1; c += 16 * kBlock) {
-        const int64_t lw = c / W - it.first_window;  // window of the chunk's first sample
-        if (c >= s0 && c + 16 <= s1 && (c + 15) / W == c / W) {
+    if (s1 - s0 == 16384 && (W & 15) == 0) {
+        // A whole 16 KiB tile of windows that are multiples of 16 samples:
+        // every 16-byte chunk lies in one window.  All four loads of a lane
+        // are issued before any store; noise goes through the workgroup pool.
+        const int lane = tid & 63, wave = tid >> 6;
+        const int64_t base = s0 + wave * 4096 + lane * 16;
+        const int sh = __builtin_ctz((unsigned)W);  // W divides 16384: a power of two
+        uint32_t v[16];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint4 t = gload16_nt(x + base + i * 1024);
+            v[4 * i] = t.x;
+            v[4 * i + 1] = t.y;
+            v[4 * i + 2] = t.z;
+            v[4 * i + 3] = t.w;
+        }
+        uint32_t cf = 0;  // bit 4i + q: dword q of chunk i holds a flagged sample
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int lw = (wave * 4096 + i * 1024 + lane * 16) >> sh;
             const WinParams p = sm.prm[lw];
-            const uint4 xv = gload16(x + c);
+            const uint32_t lo = rep_i16(p.lo * 256), hi = rep_i16(p.hi * 256);
             const uint32_t lo_u = rep_i16((p.lo + 128) * 256), hi_u = rep_i16((p.hi + 128) * 256);
-            uint32_t w4[4] = {xv.x, xv.y, xv.z, xv.w};
             uint32_t nf = 0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const uint32_t f = flag_sel_i8x4(w4[q], lo_u, hi_u);  // byte_perm selector
-                const uint32_t clipped = clamp_i8x4(w4[q], rep_i16(p.lo * 256), rep_i16(p.hi * 256));
-                const uint32_t diff = clipped ^ w4[q];
-                if (diff != 0) {
-                    nf += __popc(nonzero_byte_mask(diff)) / 8;
-                    if (d.mode == RFI_MODE_CLIP) w4[q] = clipped;
-                    else if (d.mode == RFI_MODE_ZERO) w4[q] = byte_perm(0u, w4[q], f);
-                    else w4[q] = byte_perm(noise_quad_i8((uint64_t)(d.abs_base + c + 4 * q), a.seed, d.key,
-                                                         p.m, p.sq8),
-                                           w4[q], f);
-                }
+                const uint32_t xw = v[4 * i + q];
+                const uint32_t clipped = clamp_i8x4(xw, lo, hi);
+                const uint32_t diff = clipped ^ xw;
+                nf += __popc(nonzero_byte_mask(diff)) >> 3;
+                cf |= (diff != 0 ? 1u : 0u) << (4 * i + q);
+                if constexpr (MODE == RFI_MODE_CLIP) v[4 * i + q] = clipped;
+                else if constexpr (MODE == RFI_MODE_ZERO)
+                    v[4 * i + q] = byte_perm(0u, xw, flag_sel_i8x4(xw, lo_u, hi_u));
             }
-            gstore16(y + c, make_uint4(w4[0], w4[1], w4[2], w4[3]));
             if (nf) atomicAdd(&sm.flagged[lw], nf);
-        } else {
-            for (int i = 0; i < 16; ++i) {
-                const int64_t j = c + i;
-                if (j < s0 || j >= s1) continue;
-                const int64_t wl = j / W - it.first_window;
-                const WinParams p = sm.prm[wl];
-                const int xv = gload(x + j);
-                int yv = xv;
-                if (xv < p.lo || xv > p.hi) {
-                    atomicAdd(&sm.flagged[wl], 1u);
-                    if (d.mode == RFI_MODE_ZERO) yv = 0;
-                    else if (d.mode == RFI_MODE_CLIP) yv = min(max(xv, p.lo), p.hi);
-                    else yv = noise_sample(d.abs_base + j, a.seed, d.key, p.m, p.sq8, -128, 127);
-                }
-                gstore(y + j, (int8_t)yv);
+        }
+        if constexpr (MODE == RFI_MODE_NOISE) {
+            const int64_t t0 = s0;
+            auto merged = [&](int wv, int ln, int slot, int part, uint32_t xw) -> uint32_t {
+                const int rel = wv * 4096 + slot * 1024 + ln * 16 + part * 4;
+                const int64_t c = t0 + rel;
+                const WinParams p = sm.prm[rel >> sh];
+                const uint32_t lo_u = rep_i16((p.lo + 128) * 256), hi_u = rep_i16((p.hi + 128) * 256);
+                const uint32_t nz = noise_quad_i8((uint64_t)(d.abs_base + c), a.seed, d.key, p.m, p.sq8);
+                return byte_perm(nz, xw, flag_sel_i8x4(xw, lo_u, hi_u));
+            };
+            pool_noise<4>(v, cf, sm.noise(), merged);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            gstore16_nt(y + base + i * 1024, make_uint4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]));
+    } else {
+        // Other items (irregular W, stream tails): sample by sample.
+#pragma unroll 1
+        for (int64_t j = s0 + tid; j < s1; j += kBlock) {
+            const int wl = (int)(j - s0) / W;
+            const WinParams p = sm.prm[wl];
+            const int xv = gload(x + j);
+            int yv = xv;
+            if (xv < p.lo || xv > p.hi) {
+                atomicAdd(&sm.flagged[wl], 1u);
+                if constexpr (MODE == RFI_MODE_ZERO) yv = 0;
+                else if constexpr (MODE == RFI_MODE_CLIP) yv = min(max(xv, p.lo), p.hi);
+                else yv = noise_sample(d.abs_base + j, a.seed, d.key, p.m, p.sq8, -128, 127);
             }
+            gstore(y + j, (int8_t)yv);
         }
     }
     __syncthreads();
@@ -1545,6 +1593,19 @@ hipError_t launch_i16_fused(const LaunchArgs& a, int grid, hipStream_t s)
 }
 #undef RFI_PICK
 
+__global__ __launch_bounds__(kBlock) void k_mom_apply(LaunchArgs a, const MomItem* __restrict__ items,
+                                                      const int32_t* __restrict__ dm,
+                                                      const int64_t* __restrict__ stream_woff,
+                                                      rfi_window_stats* __restrict__ stats)
+{
+    __shared__ MomSmem sm;
+    const MomItem it = items[blockIdx.x];
+    const StreamView d = resolve(a.streams[it.stream], a);
+    if (d.mode == RFI_MODE_CLIP) mom_apply_item<RFI_MODE_CLIP>(a, it, d, dm, stream_woff, stats, sm);
+    else if (d.mode == RFI_MODE_ZERO) mom_apply_item<RFI_MODE_ZERO>(a, it, d, dm, stream_woff, stats, sm);
+    else mom_apply_item<RFI_MODE_NOISE>(a, it, d, dm, stream_woff, stats, sm);
+}
+
 hipError_t launch_mom_gather(const rfi_window_stats* stats, int64_t total, uint8_t* mad, hipStream_t s)
 {
     if (total <= 0) return hipSuccess;
@@ -1553,11 +1614,18 @@ hipError_t launch_mom_gather(const rfi_window_stats* stats, int64_t total, uint8
     return hipGetLastError();
 }
 
-hipError_t launch_mom_counts(const MomStream* streams, int n_streams, const uint8_t* mad, uint32_t* hcnt,
-                             hipStream_t s)
+hipError_t launch_mom_counts(const MomStream* streams, int n_streams, int64_t max_blocks, const uint8_t* mad,
+                             uint32_t* hcnt, hipStream_t s)
 {
     if (n_streams <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mom_counts, dim3(n_streams), dim3(256), 0, s, streams, mad, hcnt);
+    if (max_blocks > 0) {
+        if (max_blocks > (1 << 30) || n_streams > 65535) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_mom_block_counts, dim3((unsigned)max_blocks, (unsigned)n_streams), dim3(256), 0, s,
+                           streams, mad, hcnt);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_mom_counts, dim3(n_streams), dim3(256), 0, s, streams, hcnt);
     return hipGetLastError();
 }
 

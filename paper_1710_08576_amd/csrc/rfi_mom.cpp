@@ -53,7 +53,7 @@ struct MomPlan {
     uint32_t* d_hcnt = nullptr;
     rfi_window_stats* d_stats = nullptr;  // used when the caller passes none
     int32_t n_streams = 0;
-    int64_t n_items = 0, total_windows = 0;
+    int64_t n_items = 0, total_windows = 0, max_blocks = 0;
     uint64_t seed = 0;
 };
 
@@ -121,6 +121,7 @@ int mom_build(int32_t n, const int64_t* L, const int32_t* W, const float* K, con
         ms[s].woff = wo;
         ms[s].nw = nw;
         ms[s].hoff = rows;
+        p->max_blocks = std::max<int64_t>(p->max_blocks, (nw + kMomBlock - 1) / kMomBlock);
         rows += nw / kMomBlock + 1 + (nw % kMomBlock ? 1 : 0);
         woff[s] = wo;
         const int64_t per = std::max<int64_t>(1, std::min<int64_t>(256, 16384 / W[s]));
@@ -158,7 +159,8 @@ int mom_execute(MomPlan* p, const void* x, void* y, rfi_window_stats* st, int32_
     int rc = plan_execute(p->stats_plan, x, y, st, s, RFI_SCHED_SPLIT);
     if (rc != RFI_OK) return rc;
     hipError_t e = launch_mom_gather(st, p->total_windows, p->d_mad, s);
-    if (e == hipSuccess) e = launch_mom_counts(p->d_streams, p->n_streams, p->d_mad, p->d_hcnt, s);
+    if (e == hipSuccess)
+        e = launch_mom_counts(p->d_streams, p->n_streams, p->max_blocks, p->d_mad, p->d_hcnt, s);
     if (e == hipSuccess)
         e = launch_mom_select(p->d_streams, p->n_streams, p->total_windows, mom_k, p->d_mad, p->d_hcnt,
                               p->d_dm, s);
