@@ -80,6 +80,7 @@ def main():
     ap.add_argument("--no-int16", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-mom", action="store_true")
+    ap.add_argument("--no-multi", action="store_true")
     ap.add_argument("--serve-blocks", type=int, default=10000,
                     help="blocks per stream in the real-time serving replay")
     ap.add_argument("--with-copy", action="store_true",
@@ -216,6 +217,8 @@ def main():
         out["int16"] = bench_int16(args, dev)
     if not args.no_mom:
         out["median_of_mad"] = bench_mom(args, dev, x, y, L)
+    if not args.no_multi:
+        out["three_outputs_one_read"] = bench_multi(args, dev, x, L, ms_step)
     if not args.no_serving:
         del x, y
         torch.cuda.empty_cache()
@@ -347,6 +350,30 @@ def bench_int16(args, dev):
     return {"workload": "60 x 2^23 int16, window 8192, k 3, noise", "ms": round(ms, 4),
             "gsamples_s": round(n / ms / 1e6, 1), "gb_s": round(ab / ms / 1e6, 1),
             "roofline_frac": round(ab / ms / 1e6 / HBM_PEAK_GBS, 4)}
+
+
+def bench_multi(args, dev, x, L, ms_three_calls):
+    """Zero, clip and noise outputs of the plain-scale batch from one read of
+    the input (the paper's side-by-side comparison of replacement options)."""
+    import torch
+
+    import paper_1710_08576_amd as rfi
+    ns, n = len(L), sum(L)
+    ys = [torch.empty_like(x) for _ in range(3)]
+    nw = rfi.layout(L, [4096] * ns)[2]
+    stream = torch.cuda.current_stream()
+    fn = lambda: rfi.mad_filter_multi(x, L, [4096] * ns, [[3.0] * ns] * 3, [[0] * ns, [1] * ns, [2] * ns],
+                                      seed=1, ys=ys, stats=False)
+    for _ in range(3):
+        fn()
+    ms = _time_events(fn, max(10, args.steps // 5), stream)
+    ab = 4 * n + 3 * 16 * nw
+    return {"workload": "plain-scale 60 x 2^24 int8, W 4096, k 3: zero, clip and noise outputs",
+            "ms": round(ms, 4), "gsamples_s_per_output": round(3 * n / ms / 1e6, 1),
+            "gb_s": round(ab / ms / 1e6, 1), "roofline_frac": round(ab / ms / 1e6 / HBM_PEAK_GBS, 4),
+            "algorithmic_bytes": "1 B/sample read + 3 B/sample written",
+            "three_single_calls_ms": round(ms_three_calls, 4),
+            "speedup_vs_three_calls": round(ms_three_calls / ms, 3)}
 
 
 def bench_mom(args, dev, x, y, L):

@@ -53,6 +53,7 @@ _SIGS = {
     "rfi_mad_filter": (ctypes.c_int, [P, P, I32, P, P, P, P, U64, P, P]),
     "rfi_mad_filter_i16": (ctypes.c_int, [P, P, I32, P, P, P, P, U64, P, P]),
     "rfi_mom_filter": (ctypes.c_int, [P, P, I32, P, P, P, P, I32, U64, P, P]),
+    "rfi_mad_filter_multi": (ctypes.c_int, [P, I32, P, I32, P, P, P, P, U64, P, P]),
     "rfi_layout": (ctypes.c_int64, [I32, P, P, P, P, P]),
     "rfi_validate": (ctypes.c_int, [I32, P, P, I32, P, P, P, P, P]),
     "rfi_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -190,6 +191,32 @@ def mad_filter(x, lengths, windows, k, mode, seed: int = 0, y=None, stats=True, 
            _stream_handle(stream))
     _check(rc, "rfi_mad_filter")
     return y, (st[:nw] if st is not None else None)
+
+
+def mad_filter_multi(x, lengths, windows, ks, modes, seed: int = 0, ys=None, stats=True, stream=None):
+    """Several outputs from one read: ks[o] / modes[o] are output o's per-stream
+    (or scalar) k and mode.  Returns (list of y, list of stats)."""
+    import torch
+    n, n_out = len(lengths), len(ks)
+    L = np.ascontiguousarray(lengths, dtype=np.int64)
+    W = _arr(windows, np.int32, n)
+    K = np.ascontiguousarray(np.concatenate([_arr(k, np.float32, n) for k in ks]))
+    M = np.ascontiguousarray(np.concatenate([_arr(m, np.int32, n) for m in modes]))
+    _, _, nw, _ = layout(L, W)
+    if x.dtype != torch.int8:
+        raise TypeError("x must be int8")
+    if ys is None:
+        ys = [torch.empty_like(x) for _ in range(n_out)]
+    sts = [torch.empty((max(nw, 1), 4), dtype=torch.int32, device=x.device) for _ in range(n_out)] \
+        if stats else None
+    yp = (ctypes.c_void_p * n_out)(*[y.data_ptr() for y in ys])
+    sp = (ctypes.c_void_p * n_out)(*[t.data_ptr() for t in sts]) if sts is not None else None
+    rc = load().rfi_mad_filter_multi(_tptr(x), n_out, ctypes.cast(yp, ctypes.c_void_p), n, _ptr(L), _ptr(W),
+                                     _ptr(K), _ptr(M), seed,
+                                     ctypes.cast(sp, ctypes.c_void_p) if sp is not None else None,
+                                     _stream_handle(stream))
+    _check(rc, "rfi_mad_filter_multi")
+    return ys, ([t[:nw] for t in sts] if sts is not None else None)
 
 
 def mom_filter(x, lengths, windows, k, mode, mom_k: int, seed: int = 0, y=None, stats=True,

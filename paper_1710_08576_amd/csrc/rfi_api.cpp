@@ -796,6 +796,7 @@ int rfi_mad_filter_i16(const int16_t* x, int16_t* y, int32_t n_streams, const in
 int rfi_shutdown(void)
 {
     rfi::mom_shutdown();
+    rfi::multi_shutdown();
     std::lock_guard<std::mutex> g(g_cache_mu);
     for (auto& kv : g_cache) rfi::plan_free(kv.second);
     g_cache.clear();

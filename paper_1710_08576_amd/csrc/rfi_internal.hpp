@@ -128,6 +128,19 @@ hipError_t launch_i16_tiles(int cls, const LaunchArgs& a, int grid, hipStream_t 
 hipError_t launch_i16_generic(const LaunchArgs& a, int grid, hipStream_t s);
 hipError_t launch_i16_fused(const LaunchArgs& a, int grid, hipStream_t s);
 
+// Several outputs from one read (int8 tile items): output o uses the
+// descriptors desc[o] (its k and mode; offsets as a.streams) and the bases
+// y_base[o], stats_base[o] (0: no statistics).  a.items: tiles of one class.
+struct MultiArgs {
+    LaunchArgs a;
+    const StreamDesc* desc[3];
+    uint64_t y_base[3];
+    uint64_t stats_base[3];
+    int32_t n_out;
+    int32_t pad;
+};
+hipError_t launch_i8_multi(int cls, const MultiArgs& ma, int grid, hipStream_t s);
+
 // Median of MAD (int8).  Windows of all streams are numbered globally in
 // the packed stats order; mad[g] is window g's own MAD, dm[g] receives the
 // lower median of the MADs of its stream's windows max(0, w-K+1) .. w.

@@ -368,6 +368,7 @@ struct I8TileSmem {
     uint32_t tot[kWPW > 1 ? kWin * 256 : 0];
     uint32_t pc[kWPW > 1 ? kWin * kPadC : 0];
     WinParams prm[kWin];
+    int32_t mad[kWin];  // statistics-only mode: each window's MAD
     uint32_t noise_counts[NS ? 4 : 0];
     __device__ NoiseScratch noise()
     {
@@ -519,7 +520,10 @@ __device__ __forceinline__ TileStats i8_tile(const StreamView& d, int64_t first,
         if (wave % WPW == 0) {
             rfi_window_stats ws;
             wide_params(pc, mb, D, d.k, W, p, ws);
-            if (lane == 0) sm.prm[wl] = p;
+            if (lane == 0) {
+                sm.prm[wl] = p;
+                if constexpr (MODE == kModeStats) sm.mad[wl] = D;
+            }
             ts.s = ws;
             ts.dst = (lane == 0 && d.stats) ? d.stats + first / W + wl : nullptr;
         }
@@ -598,6 +602,7 @@ __device__ __forceinline__ TileStats i8_tile(const StreamView& d, int64_t first,
             // Lane r of the window's group keeps the statistics of round r.
             if ((lane & (G - 1)) == r) {
                 sm.prm[wl] = p;
+                if constexpr (MODE == kModeStats) sm.mad[wl] = D;
                 ts.s = ws;
                 ts.dst = d.stats ? d.stats + first / W + wl : nullptr;
             }
@@ -1259,6 +1264,94 @@ __global__ __launch_bounds__(kBlock) void k_i16_fused(LaunchArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// Several outputs from one read (int8 tiles): the tile's windows are
+// selected once (statistics-only mode), then each output's parameters
+// (its own k) are derived from the window's median and MAD and its
+// replacement (its own mode) is applied to a copy of the tile and stored.
+// Output o is the same as a single call with that output's k and mode.
+// ---------------------------------------------------------------------------
+template <int W>
+struct I8MultiSmem {
+    I8TileSmem<W, true> t;
+    int32_t med[16384 / W];
+    float thr[16384 / W];
+    uint32_t nfl[16384 / W];
+};
+
+template <int CLS>
+__global__ __launch_bounds__(kBlock) void k_i8_multi(MultiArgs ma)
+{
+    constexpr int W = 512 << CLS;
+    constexpr int kWin = 16384 / W;
+    __shared__ I8MultiSmem<W> sm;
+    const LaunchArgs& a = ma.a;
+    const Item item = a.items[blockIdx.x];
+    const int tid = (int)threadIdx.x, lane = lane_id();
+    const int wbase = (tid >> 6) * 4096;
+    const StreamView d0 = resolve(a.streams[item.stream], a);
+    uint32_t v[16];
+    tile_load(d0, item.first, v);
+    (void)i8_tile<W, true, kModeStats>(d0, item.first, a.seed, sm.t, v);
+    __syncthreads();
+    if (tid < kWin) sm.med[tid] = sm.t.prm[tid].m;
+    for (int o = 0; o < ma.n_out; ++o) {
+        LaunchArgs ao = a;
+        ao.streams = ma.desc[o];
+        ao.y_base = ma.y_base[o];
+        ao.stats_base = ma.stats_base[o];
+        ao.no_stats = ma.stats_base[o] == 0 ? 1 : 0;
+        const StreamView d = resolve(ao.streams[item.stream], ao);
+        __syncthreads();  // the previous output is done with prm and the scratch
+        if (tid < kWin) {
+            const int m = sm.med[tid];
+            float sig;
+            const float t = threshold_of(sm.t.mad[tid], d.k, sig);
+            const int T = (int)floorf(t);
+            WinParams p;
+            p.lo = max(m - T, -128);
+            p.hi = min(m + T, 127);
+            p.m = m;
+            p.sq8 = (int)__fmul_rn(sig, 256.0f);
+            sm.t.prm[tid] = p;
+            sm.thr[tid] = t;
+            sm.nfl[tid] = 0;
+        }
+        __syncthreads();
+        uint32_t w[16];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int win = (wbase + i * 1024 + lane * 16) / W;
+            const WinParams p = sm.t.prm[win];
+            const uint32_t lo = rep_i16(p.lo * 256), hi = rep_i16(p.hi * 256);
+            uint32_t nf = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                w[4 * i + j] = v[4 * i + j];
+                nf += __popc(nonzero_byte_mask(clamp_i8x4(v[4 * i + j], lo, hi) ^ v[4 * i + j])) >> 3;
+            }
+            if (nf) atomicAdd(&sm.nfl[win], nf);
+        }
+        auto bounds = [&](int i) { return sm.t.prm[(wbase + i * 1024 + lane * 16) / W]; };
+        if (d.mode == RFI_MODE_CLIP) i8_replace<W, true, RFI_MODE_CLIP>(d, item.first, a.seed, sm.t, w, bounds);
+        else if (d.mode == RFI_MODE_ZERO) i8_replace<W, true, RFI_MODE_ZERO>(d, item.first, a.seed, sm.t, w, bounds);
+        else i8_replace<W, true, RFI_MODE_NOISE>(d, item.first, a.seed, sm.t, w, bounds);
+        uint8_t* yt = static_cast<uint8_t*>(d.y) + item.first + wbase + lane * 16;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            gstore16_nt(yt + i * 1024, make_uint4(w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]));
+        __syncthreads();
+        if (tid < kWin && d.stats) {
+            rfi_window_stats st;
+            st.median = sm.med[tid];
+            st.mad = sm.t.mad[tid];
+            st.n_flagged = sm.nfl[tid];
+            st.threshold = sm.thr[tid];
+            d.stats[item.first / W + tid] = st;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Median of MAD (Eq. (3)), int8: the MADs of the first pass are gathered,
 // counted per stream in blocks of 64 windows, and each window's lower
 // median of the MADs of its K-window history is found by a binary search
@@ -1604,6 +1697,24 @@ __global__ __launch_bounds__(kBlock) void k_mom_apply(LaunchArgs a, const MomIte
     if (d.mode == RFI_MODE_CLIP) mom_apply_item<RFI_MODE_CLIP>(a, it, d, dm, stream_woff, stats, sm);
     else if (d.mode == RFI_MODE_ZERO) mom_apply_item<RFI_MODE_ZERO>(a, it, d, dm, stream_woff, stats, sm);
     else mom_apply_item<RFI_MODE_NOISE>(a, it, d, dm, stream_woff, stats, sm);
+}
+
+hipError_t launch_i8_multi(int cls, const MultiArgs& ma, int grid, hipStream_t s)
+{
+    if (ma.a.n_items <= 0) return hipSuccess;
+    void (*k)(MultiArgs) = nullptr;
+    switch (cls) {
+        case 0: k = k_i8_multi<0>; break;
+        case 1: k = k_i8_multi<1>; break;
+        case 2: k = k_i8_multi<2>; break;
+        case 3: k = k_i8_multi<3>; break;
+        case 4: k = k_i8_multi<4>; break;
+        case 5: k = k_i8_multi<5>; break;
+        default: return hipErrorInvalidValue;
+    }
+    MultiArgs args = ma;
+    void* kargs[] = {&args};
+    return hipLaunchKernel(reinterpret_cast<const void*>(k), dim3(grid), dim3(kBlock), kargs, 0, s);
 }
 
 hipError_t launch_mom_gather(const rfi_window_stats* stats, int64_t total, uint8_t* mad, hipStream_t s)

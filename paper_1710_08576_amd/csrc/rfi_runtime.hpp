@@ -22,7 +22,8 @@ int plan_build(int elem, int32_t n, const int64_t* L, const int32_t* W, const fl
 int plan_execute(rfi_plan* p, const void* x, void* y, rfi_window_stats* st, hipStream_t s,
                  int sched_override);
 void plan_free(rfi_plan* p);
-// Frees the median-of-MAD work tables (rfi_shutdown).
+// Free the median-of-MAD and multi-output work tables (rfi_shutdown).
 void mom_shutdown();
+void multi_shutdown();
 
 }  // namespace rfi
