@@ -123,14 +123,17 @@ const char* rfi_status_string(int status);
 const char* rfi_version(void);
 
 /* Several outputs from one read, int8: the paper's test arrangement in
- * which one input is filtered with different replacement options side by
- * side (Sec. III).  n_out (1..3) outputs y[0..n_out); output o uses the
+ * which one input is copied to several filters with different thresholds
+ * and replacement options side by side (Sec. III-A, second test scheme).
+ * n_out (1..3) outputs y[0..n_out); output o uses the
  * per-stream arrays k[o * n_streams + s] and mode[o * n_streams + s] and is
  * bit-identical to rfi_mad_filter(x, y[o], ..., that k, that mode, seed,
  * stats_out[o], stream).  stats_out may be NULL, as may any stats_out[o].
  * Outputs must not overlap x or each other (RFI_ERR_INVALID); other
- * arguments and errors as rfi_mad_filter.  Windows of a tile class are read
- * once for all outputs; other windows once per output. */
+ * arguments and errors as rfi_mad_filter.  The outputs with no noise
+ * stream share one read of x for the windows of a tile class (other
+ * windows: one read per output); an output with noise streams is computed
+ * by a pass of its own. */
 int rfi_mad_filter_multi(const int8_t* x, int32_t n_out, int8_t* const* y, int32_t n_streams,
                          const int64_t* lengths, const int32_t* windows, const float* k,
                          const int32_t* mode, uint64_t seed, rfi_window_stats* const* stats_out,

@@ -139,6 +139,7 @@ struct MultiArgs {
     int32_t n_out;
     int32_t pad;
 };
+// Outputs in zero or clip mode only.
 hipError_t launch_i8_multi(int cls, const MultiArgs& ma, int grid, hipStream_t s);
 
 // Median of MAD (int8).  Windows of all streams are numbered globally in

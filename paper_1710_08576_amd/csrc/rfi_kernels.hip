@@ -1272,12 +1272,15 @@ __global__ __launch_bounds__(kBlock) void k_i16_fused(LaunchArgs a)
 // ---------------------------------------------------------------------------
 template <int W>
 struct I8MultiSmem {
-    I8TileSmem<W, true> t;
+    I8TileSmem<W, false> t;
     int32_t med[16384 / W];
     float thr[16384 / W];
     uint32_t nfl[16384 / W];
 };
 
+// Zero and clip outputs only: a noise output would keep a second copy of
+// the tile and the pooled draws in registers, which costs more occupancy
+// than a second read of the input (noise outputs are separate passes).
 template <int CLS>
 __global__ __launch_bounds__(kBlock) void k_i8_multi(MultiArgs ma)
 {
@@ -1291,9 +1294,10 @@ __global__ __launch_bounds__(kBlock) void k_i8_multi(MultiArgs ma)
     const StreamView d0 = resolve(a.streams[item.stream], a);
     uint32_t v[16];
     tile_load(d0, item.first, v);
-    (void)i8_tile<W, true, kModeStats>(d0, item.first, a.seed, sm.t, v);
+    (void)i8_tile<W, false, kModeStats>(d0, item.first, a.seed, sm.t, v);
     __syncthreads();
     if (tid < kWin) sm.med[tid] = sm.t.prm[tid].m;
+#pragma unroll 1
     for (int o = 0; o < ma.n_out; ++o) {
         LaunchArgs ao = a;
         ao.streams = ma.desc[o];
@@ -1317,28 +1321,28 @@ __global__ __launch_bounds__(kBlock) void k_i8_multi(MultiArgs ma)
             sm.nfl[tid] = 0;
         }
         __syncthreads();
-        uint32_t w[16];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int win = (wbase + i * 1024 + lane * 16) / W;
-            const WinParams p = sm.t.prm[win];
-            const uint32_t lo = rep_i16(p.lo * 256), hi = rep_i16(p.hi * 256);
-            uint32_t nf = 0;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                w[4 * i + j] = v[4 * i + j];
-                nf += __popc(nonzero_byte_mask(clamp_i8x4(v[4 * i + j], lo, hi) ^ v[4 * i + j])) >> 3;
-            }
-            if (nf) atomicAdd(&sm.nfl[win], nf);
-        }
-        auto bounds = [&](int i) { return sm.t.prm[(wbase + i * 1024 + lane * 16) / W]; };
-        if (d.mode == RFI_MODE_CLIP) i8_replace<W, true, RFI_MODE_CLIP>(d, item.first, a.seed, sm.t, w, bounds);
-        else if (d.mode == RFI_MODE_ZERO) i8_replace<W, true, RFI_MODE_ZERO>(d, item.first, a.seed, sm.t, w, bounds);
-        else i8_replace<W, true, RFI_MODE_NOISE>(d, item.first, a.seed, sm.t, w, bounds);
         uint8_t* yt = static_cast<uint8_t*>(d.y) + item.first + wbase + lane * 16;
+        {
+            // zero / clip: slot by slot, four registers at a time
+            const bool clip = d.mode == RFI_MODE_CLIP;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            gstore16_nt(yt + i * 1024, make_uint4(w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]));
+            for (int i = 0; i < 4; ++i) {
+                const int win = (wbase + i * 1024 + lane * 16) / W;
+                const WinParams p = sm.t.prm[win];
+                const uint32_t lo = rep_i16(p.lo * 256), hi = rep_i16(p.hi * 256);
+                const uint32_t lo_u = rep_i16((p.lo + 128) * 256), hi_u = rep_i16((p.hi + 128) * 256);
+                uint32_t r[4], nf = 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t xw = v[4 * i + j];
+                    const uint32_t c = clamp_i8x4(xw, lo, hi);
+                    nf += __popc(nonzero_byte_mask(c ^ xw)) >> 3;
+                    r[j] = clip ? c : byte_perm(0u, xw, flag_sel_i8x4(xw, lo_u, hi_u));
+                }
+                if (nf) atomicAdd(&sm.nfl[win], nf);
+                gstore16_nt(yt + i * 1024, make_uint4(r[0], r[1], r[2], r[3]));
+            }
+        }
         __syncthreads();
         if (tid < kWin && d.stats) {
             rfi_window_stats st;

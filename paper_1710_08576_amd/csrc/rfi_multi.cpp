@@ -2,10 +2,14 @@
 //
 // Each output o has its own threshold multiple and replacement mode per
 // stream; output o is bit-identical to rfi_mad_filter with that output's k
-// and mode.  Tiles of whole windows (W a tile class) are read once and
-// written n_out times by k_i8_multi; the remaining windows (stream tails,
-// irregular W) go through the generic kernel once per output.  Work tables
-// are kept per argument signature.
+// and mode.  Outputs with no noise stream share one read: tiles of whole
+// windows (W a tile class) are read once and written once per output by
+// k_i8_multi; the remaining windows (stream tails, irregular W) go through
+// the generic kernel once per output.  An output with noise streams is a
+// single-output call of its own (a noise output in the shared kernel keeps
+// a second copy of the tile and the pooled draws in registers, which cost
+// more occupancy than a second read saves).  Work tables are kept per
+// argument signature.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -196,15 +200,45 @@ int rfi_mad_filter_multi(const int8_t* x, int32_t n_out, int8_t* const* y, int32
         }
     }
     if (n_streams == 0 || elems == 0) return RFI_OK;
+    // Outputs with a noise stream run alone; the others share one read.
+    std::vector<int> shared;
+    for (int o = 0; o < n_out; ++o) {
+        const int32_t* mo = mode + (int64_t)o * n_streams;
+        if (std::find(mo, mo + n_streams, (int32_t)RFI_MODE_NOISE) != mo + n_streams) {
+            int rc = rfi_mad_filter(x, y[o], n_streams, lengths, windows, k + (int64_t)o * n_streams, mo,
+                                    seed, stats_out ? stats_out[o] : nullptr, stream);
+            if (rc != RFI_OK) return rc;
+        } else {
+            shared.push_back(o);
+        }
+    }
+    if (shared.empty()) return RFI_OK;
+    if (shared.size() == 1) {
+        const int o = shared[0];
+        return rfi_mad_filter(x, y[o], n_streams, lengths, windows, k + (int64_t)o * n_streams,
+                              mode + (int64_t)o * n_streams, seed, stats_out ? stats_out[o] : nullptr, stream);
+    }
+    const int32_t ns = (int32_t)shared.size();
+    std::vector<float> ks((size_t)ns * n_streams);
+    std::vector<int32_t> ms((size_t)ns * n_streams);
+    std::vector<int8_t*> ys(ns);
+    std::vector<rfi_window_stats*> sts(ns);
+    for (int i = 0; i < ns; ++i) {
+        const int o = shared[i];
+        std::memcpy(&ks[(size_t)i * n_streams], k + (int64_t)o * n_streams, sizeof(float) * n_streams);
+        std::memcpy(&ms[(size_t)i * n_streams], mode + (int64_t)o * n_streams, sizeof(int32_t) * n_streams);
+        ys[i] = y[o];
+        sts[i] = stats_out ? stats_out[o] : nullptr;
+    }
     MultiKey key;
     if (hipGetDevice(&key.device) != hipSuccess) key.device = 0;
     key.seed = seed;
-    key.n_out = n_out;
+    key.n_out = ns;
     key.L.assign(lengths, lengths + n_streams);
     key.W.assign(windows, windows + n_streams);
-    key.K.resize((size_t)n_out * n_streams);
-    std::memcpy(key.K.data(), k, sizeof(float) * key.K.size());
-    key.M.assign(mode, mode + (size_t)n_out * n_streams);
+    key.K.resize(ks.size());
+    std::memcpy(key.K.data(), ks.data(), sizeof(float) * ks.size());
+    key.M = ms;
     std::lock_guard<std::mutex> g(g_multi_mu);
     MultiPlan* p = nullptr;
     auto it = g_multi.find(key);
@@ -217,12 +251,12 @@ int rfi_mad_filter_multi(const int8_t* x, int32_t n_out, int8_t* const* y, int32
             g_multi.erase(old);
             g_multi_order.erase(g_multi_order.begin());
         }
-        int rc = multi_build(n_out, n_streams, lengths, windows, k, mode, seed, &p);
+        int rc = multi_build(ns, n_streams, lengths, windows, ks.data(), ms.data(), seed, &p);
         if (rc != RFI_OK) return rc;
         g_multi[key] = p;
         g_multi_order.push_back(key);
     }
-    return multi_execute(p, x, y, stats_out, (hipStream_t)stream);
+    return multi_execute(p, x, ys.data(), sts.data(), (hipStream_t)stream);
 }
 
 }  // extern "C"
