@@ -7,7 +7,9 @@ binding) never does, and shares no code with it.
 The arithmetic lives in ``rfi_oracle.c`` (plain C, full sort per window);
 this module only builds it with gcc and marshals numpy arrays through ctypes.
 Paper: Buch et al., "Implementing and Characterizing Real-time Broadband RFI
-Excision for the GMRT Wideband Backend", Sec. II-D, Eqs. (1)-(2).
+Excision for the GMRT Wideband Backend", Sec. II-D, Eqs. (1)-(3); the
+improvement metric of Sec. III-A (block power, mean-to-RMS ratio,
+improvement in dB) is plain numpy at the end of this module.
 """
 from __future__ import annotations
 
@@ -163,3 +165,67 @@ def mom_filter_batch(x, lengths, windows, k, mode, mom_k: int, seed: int = 0,
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     return y, st[:total]
+
+
+# ---------------------------------------------------------------------------
+# Improvement metric (Sec. III-A): the filter's effect is scored as
+# 10 log10 of the ratio of the average mean-to-RMS ratios of the filtered
+# and unfiltered integrated power.  Plain numpy, integers exact, ratios fp64.
+# ---------------------------------------------------------------------------
+
+def block_power(x, lengths, block: int) -> np.ndarray:
+    """Integrated power (Sec. III-A): sum of x^2 over each block of
+    ``block`` consecutive samples of each stream of a packed batch (streams at 64-element-aligned offsets, a short
+    final block is a block of its own); int64, blocks of stream s first."""
+    x = np.asarray(x)
+    out = []
+    off = 0
+    for L in lengths:
+        L = int(L)
+        s = x[off:off + L].astype(np.int64)
+        for b in range(0, L, block):
+            v = s[b:b + block]
+            out.append(int(np.dot(v, v)))
+        off += (L + 63) // 64 * 64
+    return np.array(out, dtype=np.int64)
+
+
+def mean_to_rms(power, seg: int) -> float:
+    """Average mean-to-RMS ratio (Sec. III-A), read as: the average over
+    consecutive segments of ``seg`` values of the ratio of
+    the segment's mean to its RMS deviation about that mean (population
+    form).  Values after the last whole segment are not used; no whole
+    segment gives NaN.  A segment with no deviation gives +inf (or NaN when
+    its mean is 0 too), as IEEE division does."""
+    p = np.asarray(power, dtype=np.float64)
+    n_seg = len(p) // seg
+    if n_seg == 0:
+        return float("nan")
+    ratios = []
+    for i in range(n_seg):
+        v = p[i * seg:(i + 1) * seg]
+        mu = v.sum() / seg
+        rms = np.sqrt(((v - mu) ** 2).sum() / seg)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            ratios.append(np.float64(mu) / np.float64(rms))
+    return float(np.sum(ratios) / n_seg)
+
+
+def improvement(power_u, power_f, lengths, block: int, seg: int) -> np.ndarray:
+    """Improvement metric (Sec. III-A), per stream (S_U, S_F, I): the
+    average mean-to-RMS ratios of the
+    unfiltered and filtered block powers (whole blocks only) and the
+    improvement I = 10 log10(S_F / S_U) in dB (positive when filtering
+    steadies the integrated power).  ``power_*`` as from block_power."""
+    out = np.zeros((len(lengths), 3), dtype=np.float64)
+    off = 0
+    for s, L in enumerate(lengths):
+        L = int(L)
+        nb = (L + block - 1) // block
+        full = L // block
+        su = mean_to_rms(np.asarray(power_u)[off:off + full], seg)
+        sf = mean_to_rms(np.asarray(power_f)[off:off + full], seg)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            out[s] = (su, sf, 10.0 * np.log10(np.float64(sf) / np.float64(su)))
+        off += nb
+    return out

@@ -105,6 +105,32 @@ def gen_stream(spec: StreamSpec, seed: int, tag: int, s: int, device="cpu") -> t
     raise ValueError(spec.dtype)
 
 
+def emulator_mask(length: int, on: int, period: int, phase: int = 0, device="cpu") -> torch.Tensor:
+    """Boolean mask of the samples inside the periodic bursts of an RFI
+    emulator: the first burst starts at sample ``phase``; sample i is inside
+    iff i >= phase and (i - phase) mod period < on."""
+    i = torch.arange(length, dtype=torch.int64, device=device)
+    return (i >= phase) & (torch.remainder(i - phase, period) < on)
+
+
+def gen_emulator_stream(length: int, sigma: float, on: int, period: int, phase: int,
+                        burst_db: float, seed: int, s: int, device="cpu") -> torch.Tensor:
+    """int8 stream with periodic broadband bursts, the synthetic stand-in for
+    the analog RFI emulator of Sec. III-B (an on-period of 64 us every 2 s at
+    800 Msample/s is on = 51 200 samples; the period is a parameter so that
+    short streams still hold several bursts).  Outside a burst the samples
+    are round(N(0, sigma^2)); inside, Gaussian noise whose power is
+    ``burst_db`` above the system noise (the 10-20 dB of Sec. II-A) is added
+    before rounding; the sum saturates to int8."""
+    g = _gen(seed, 31, s, device)
+    base = torch.randn(length, generator=g, device=device, dtype=torch.float32) * sigma
+    extra = torch.randn(length, generator=g, device=device, dtype=torch.float32)
+    extra = extra * (sigma * 10.0 ** (burst_db / 20.0))
+    inside = emulator_mask(length, on, period, phase, device)
+    v = torch.round(base + torch.where(inside, extra, torch.zeros_like(extra)))
+    return torch.clamp(v, I8_MIN, I8_MAX).to(torch.int8)
+
+
 def align_up(n: int, a: int = ALIGN) -> int:
     return (n + a - 1) // a * a
 
