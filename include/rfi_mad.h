@@ -78,6 +78,7 @@ typedef struct {
 /* Limits checked by rfi_validate. */
 #define RFI_MAX_WINDOW 65536
 #define RFI_MAX_K 1.0e4f
+#define RFI_MAX_BLOCK (1 << 30) /* rfi_block_power, rfi_improvement */
 
 /* ------------------------------------------------------------------ */
 /* Batch filtering (Sec. II-D, Eqs. (1)-(2)).                          */
@@ -118,6 +119,39 @@ int rfi_validate(int32_t elem_size, const void* x, const void* y, int32_t n_stre
 /* Static text for a status code; for RFI_ERR_HIP, the last HIP error seen
  * by this thread. */
 const char* rfi_status_string(int status);
+
+/* Integrated power for the improvement metric (Sec. III-A, which scores a
+ * filter on integrated power; here it is integrated over blocks of time
+ * samples).  For each stream s of a packed batch (the layout above) and
+ * each block b of `block` consecutive samples (a short final block is a
+ * block of its own): power_out[boff_s + b] = sum of x^2 over the block,
+ * exact, with boff_s = sum_{j<s} ceil(L_j / block).
+ *   x          device, int8 (elem_bytes 1) or int16 (elem_bytes 2),
+ *              16-byte aligned; read only (padding elements are read).
+ *   block      1 <= block <= RFI_MAX_BLOCK.
+ *   power_out  device int64 [sum_s ceil(L_s / block)], 8-byte aligned,
+ *              must not overlap x.
+ * Errors: RFI_ERR_INVALID (sizes, NULL with work to do, overlap),
+ * RFI_ERR_ALIGN, RFI_ERR_NOMEM, RFI_ERR_HIP.  Asynchronous on `stream`.
+ * Blocks of more than 64 KiB are summed in 64 KiB parts (a work buffer of
+ * 8 bytes per part is kept by the library per lengths/block signature). */
+int rfi_block_power(const void* x, int32_t elem_bytes, int32_t n_streams, const int64_t* lengths,
+                    int32_t block, int64_t* power_out, void* stream);
+
+/* Improvement metric (Sec. III-A) from the block powers of an unfiltered
+ * (power_u) and a filtered (power_f) batch, both laid out as rfi_block_power
+ * writes them for the same lengths and block.  Per stream, over its whole
+ * blocks only (a short final block is not used): the values are cut into
+ * floor(whole_blocks / seg_blocks) segments of seg_blocks consecutive blocks
+ * (the rest is not used); a segment's mean-to-RMS ratio is its mean over
+ * the population RMS of its deviations from that mean; S is the average of
+ * those ratios.  out[3 s + 0] = S_U, out[3 s + 1] = S_F,
+ * out[3 s + 2] = 10 log10(S_F / S_U) in dB (positive when the filtered power
+ * is steadier), binary64 on the device (device buffer, 8-byte aligned).
+ * No whole segment: NaN; a segment without deviation: +inf (IEEE division).
+ * seg_blocks >= 1.  Errors as rfi_block_power.  Asynchronous on `stream`. */
+int rfi_improvement(const int64_t* power_u, const int64_t* power_f, int32_t n_streams, const int64_t* lengths,
+                    int32_t block, int32_t seg_blocks, double* out, void* stream);
 
 /* Version string of the library build. */
 const char* rfi_version(void);

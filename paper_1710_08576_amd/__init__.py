@@ -9,6 +9,6 @@ zero, by the threshold about the median, or by Philox-driven digital noise
 generator used by tests and benchmarks.
 """
 from ._lib import (  # noqa: F401
-    CLIP, NOISE, ZERO, SCHEDULES, STATS_DTYPE, Plan, RfiError, Server, layout, load, mad_filter, mad_filter_multi, mom_filter,
-    stats_numpy, validate,
+    CLIP, NOISE, ZERO, SCHEDULES, STATS_DTYPE, Plan, RfiError, Server, block_power, improvement, layout, load,
+    mad_filter, mad_filter_multi, mom_filter, n_blocks, stats_numpy, validate,
 )

@@ -54,6 +54,8 @@ _SIGS = {
     "rfi_mad_filter_i16": (ctypes.c_int, [P, P, I32, P, P, P, P, U64, P, P]),
     "rfi_mom_filter": (ctypes.c_int, [P, P, I32, P, P, P, P, I32, U64, P, P]),
     "rfi_mad_filter_multi": (ctypes.c_int, [P, I32, P, I32, P, P, P, P, U64, P, P]),
+    "rfi_block_power": (ctypes.c_int, [P, I32, I32, P, I32, P, P]),
+    "rfi_improvement": (ctypes.c_int, [P, P, I32, P, I32, I32, P, P]),
     "rfi_layout": (ctypes.c_int64, [I32, P, P, P, P, P]),
     "rfi_validate": (ctypes.c_int, [I32, P, P, I32, P, P, P, P, P]),
     "rfi_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -442,3 +444,41 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def n_blocks(lengths, block: int) -> int:
+    """Number of blocks (a short final block counts) over all streams; 0 for
+    a block below 1 (the library rejects it)."""
+    if block < 1:
+        return 0
+    return int(sum((int(L) + block - 1) // block for L in lengths))
+
+
+def block_power(x, lengths, block: int, out=None, stream=None):
+    """Sum of x^2 over each block of ``block`` samples of each stream of a
+    packed int8/int16 CUDA tensor; returns an int64 tensor, blocks of stream
+    0 first (Sec. III-A integrated power)."""
+    import torch
+    L = np.ascontiguousarray(lengths, dtype=np.int64)
+    if x.dtype not in (torch.int8, torch.int16):
+        raise TypeError("x must be int8 or int16")
+    nb = n_blocks(L, block)
+    if out is None:
+        out = torch.empty(max(nb, 1), dtype=torch.int64, device=x.device)
+    rc = load().rfi_block_power(_tptr(x), x.element_size(), len(L), _ptr(L), int(block), _tptr(out),
+                                _stream_handle(stream))
+    _check(rc, "rfi_block_power")
+    return out[:nb]
+
+
+def improvement(power_u, power_f, lengths, block: int, seg_blocks: int, out=None, stream=None):
+    """Per stream (S_U, S_F, I dB) from unfiltered and filtered block powers
+    (Sec. III-A improvement metric); returns a float64 [n_streams, 3] tensor."""
+    import torch
+    L = np.ascontiguousarray(lengths, dtype=np.int64)
+    if out is None:
+        out = torch.empty((max(len(L), 1), 3), dtype=torch.float64, device=power_u.device)
+    rc = load().rfi_improvement(_tptr(power_u), _tptr(power_f), len(L), _ptr(L), int(block), int(seg_blocks),
+                                _tptr(out), _stream_handle(stream))
+    _check(rc, "rfi_improvement")
+    return out[:len(L)]

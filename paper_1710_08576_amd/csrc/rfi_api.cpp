@@ -797,6 +797,7 @@ int rfi_shutdown(void)
 {
     rfi::mom_shutdown();
     rfi::multi_shutdown();
+    rfi::power_shutdown();
     std::lock_guard<std::mutex> g(g_cache_mu);
     for (auto& kv : g_cache) rfi::plan_free(kv.second);
     g_cache.clear();

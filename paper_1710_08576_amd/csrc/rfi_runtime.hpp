@@ -25,5 +25,7 @@ void plan_free(rfi_plan* p);
 // Free the median-of-MAD and multi-output work tables (rfi_shutdown).
 void mom_shutdown();
 void multi_shutdown();
+// Free the block-power work tables (rfi_shutdown).
+void power_shutdown();
 
 }  // namespace rfi
