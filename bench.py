@@ -81,6 +81,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-mom", action="store_true")
     ap.add_argument("--no-multi", action="store_true")
+    ap.add_argument("--no-analysis", action="store_true",
+                    help="skip the improvement-metric and MAD-breakdown sections")
     ap.add_argument("--serve-blocks", type=int, default=10000,
                     help="blocks per stream in the real-time serving replay")
     ap.add_argument("--with-copy", action="store_true",
@@ -219,6 +221,9 @@ def main():
         out["median_of_mad"] = bench_mom(args, dev, x, y, L)
     if not args.no_multi:
         out["three_outputs_per_call"] = bench_multi(args, dev, x, L)
+    if not args.no_analysis:
+        out["improvement_metric"] = bench_improvement(args, dev, x, y, L)
+        out["mad_breakdown"] = bench_breakdown(args, dev)
     if not args.no_serving:
         del x, y
         torch.cuda.empty_cache()
@@ -390,6 +395,87 @@ def bench_multi(args, dev, x, L):
     return {"workload": "plain-scale 60 x 2^24 int8, W 4096, three outputs per call",
             "algorithmic_bytes": "per read of x 1 B/sample, per output 1 B/sample written (no statistics)",
             "windows": nw, **out}
+
+
+def bench_improvement(args, dev, x, y, L):
+    """Improvement metric (Sec. III-A) of each replacement mode on the
+    plain-scale batch (W 4096, k 3): power integrated over blocks of 2^20
+    samples (1.31 ms at 800 Msample/s, the beamformer's 1.3 ms), mean-to-RMS
+    ratios over segments of 16 blocks, 10 log10(S_F / S_U) per stream."""
+    import numpy as np
+    import torch
+
+    import paper_1710_08576_amd as rfi
+    ns, n = len(L), sum(L)
+    block, seg = 1 << 20, 16
+    W = [4096] * ns
+    stream = torch.cuda.current_stream()
+    nb = rfi.n_blocks(L, block)
+    pu = torch.empty(nb, dtype=torch.int64, device=dev)
+    pf = torch.empty(nb, dtype=torch.int64, device=dev)
+    res = torch.empty((ns, 3), dtype=torch.float64, device=dev)
+    rfi.block_power(x, L, block, out=pu)
+    reps = max(10, args.steps // 5)
+    ms_pow = _time_events(lambda: rfi.block_power(x, L, block, out=pu), reps, stream)
+    ms_imp = _time_events(lambda: rfi.improvement(pu, pf, L, block, seg, out=res), reps, stream)
+    ab = n + 8 * nb
+    out = {"workload": "plain-scale 60 x 2^24 int8, W 4096, k 3; blocks of 2^20 samples, segments of 16 blocks",
+           "block_power": {"ms": round(ms_pow, 4), "gb_s": round(ab / ms_pow / 1e6, 1),
+                           "roofline_frac": round(ab / ms_pow / 1e6 / HBM_PEAK_GBS, 4),
+                           "algorithmic_bytes": "1 B/sample read + 8 B/block written"},
+           "improvement_kernel_ms": round(ms_imp, 4)}
+    for name, m in (("zero", 0), ("clip", 1), ("noise", 2)):
+        rfi.mad_filter(x, L, W, [3.0] * ns, [m] * ns, seed=1, y=y, stats=False)
+        rfi.block_power(y, L, block, out=pf)
+        r = rfi.improvement(pu, pf, L, block, seg, out=res).cpu().numpy()
+        out[name + "_db"] = {"median": round(float(np.median(r[:, 2])), 2), "min": round(float(r[:, 2].min()), 2),
+                             "max": round(float(r[:, 2].max()), 2)}
+    out["s_unfiltered_median"] = round(float(np.median(r[:, 0])), 2)
+    return out
+
+
+def bench_breakdown(args, dev):
+    """MAD breakdown on emulator bursts (Sec. III-B): 60 streams of 2^24
+    int8 samples (sigma U[6, 20]), Gaussian bursts 15 dB above the noise,
+    one every 2^22 samples from sample 2^20 on; per burst length the
+    fraction of burst samples flagged by MAD with W 16384 and 4096 and by the
+    median of MAD (W 4096, 4096 windows), all clip mode (clip changes
+    exactly the flagged samples), and the time of each filter."""
+    import torch
+
+    import paper_1710_08576_amd as rfi
+    from paper_1710_08576_amd import synth
+    specs = synth.plain_scale(60, 1 << 24, 4096, rfi.CLIP)
+    ns, L = len(specs), 1 << 24
+    lengths = [L] * ns
+    period, phase = 1 << 22, 1 << 20
+    so = rfi.layout(lengths, [4096] * ns)[0]
+    stream = torch.cuda.current_stream()
+    out = {"workload": "emulator bursts: 60 x 2^24 int8, 15 dB Gaussian bursts every 2^22 samples from 2^20; "
+                       "on-lengths in samples at 800 Msample/s (51200 = 64 us)"}
+    for on in (2048, 8192, 16384, 51200):
+        x = torch.zeros(int(so[-1]) + synth.align_up(L), dtype=torch.int8, device=dev)
+        for s, sp in enumerate(specs):
+            x[so[s]:so[s] + L] = synth.gen_emulator_stream(L, sp.sigma, on, period, phase, 15.0, 0, s, device=dev)
+        mask = synth.emulator_mask(L, on, period, phase, device=dev)
+        yb = torch.empty_like(x)
+        row = {}
+        for name, fn in (("mad_w16384", lambda: rfi.mad_filter(x, lengths, [16384] * ns, [3.0] * ns, [1] * ns,
+                                                                seed=1, y=yb, stats=False)[0]),
+                         ("mad_w4096", lambda: rfi.mad_filter(x, lengths, [4096] * ns, [3.0] * ns, [1] * ns,
+                                                              seed=1, y=yb, stats=False)[0]),
+                         ("mom_w4096_k4096", lambda: rfi.mom_filter(x, lengths, [4096] * ns, [3.0] * ns, [1] * ns,
+                                                                    4096, seed=1, y=yb, stats=False)[0])):
+            y = fn()
+            flagged = 0
+            for s in range(ns):
+                flagged += int(((y[so[s]:so[s] + L] != x[so[s]:so[s] + L]) & mask).sum())
+            det = flagged / (ns * int(mask.sum()))
+            ms = _time_events(fn, 5, stream)
+            row[name] = {"detected": round(det, 4), "ms": round(ms, 4)}
+        out[f"on_{on}"] = row
+        del x, yb
+    return out
 
 
 def bench_mom(args, dev, x, y, L):
