@@ -126,7 +126,8 @@ def write_trace_markdown(trace_dir, title, commands, out, bench_file=None):
     for (name, wgs), d in sorted(groups.items(), key=lambda kv: (kv[0][0], kv[0][1])):
         if "rfi::" not in name:
             continue
-        lines.append(f"| `{name.split('(')[0]}` | {wgs} | {len(d)} | {statistics.mean(d) / 1e3:.1f} | "
+        short = name.replace("(anonymous namespace)::", "").split("(")[0]
+        lines.append(f"| `{short}` | {wgs} | {len(d)} | {statistics.mean(d) / 1e3:.1f} | "
                      f"{min(d) / 1e3:.1f} | {max(d) / 1e3:.1f} |")
     if bench_file and os.path.exists(bench_file):
         with open(bench_file) as f:
