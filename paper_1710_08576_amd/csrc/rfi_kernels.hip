@@ -794,7 +794,11 @@ __device__ __forceinline__ uint2 noise_quad_i16(uint64_t j0, uint64_t seed, uint
 // hundred of the median, so a coarse pass over the top 8 bits would send
 // almost every sample to a handful of bins and serialise the LDS atomics;
 // 4096 coarse bins (16 values each) spread them over hundreds.
-constexpr int kI16Reps = 2;  // replicas of the coarse histogram (lane & 1)
+// One copy of the coarse histogram: with the swizzle below the atomics of a
+// Gaussian-like window spread over the banks well enough, and the smaller
+// footprint (16 KiB) leaves room for more workgroups per CU than two
+// copies did.
+constexpr int kI16Reps = 1;  // replicas of the coarse histogram (replica = lane % R)
 
 struct I16TileSmem {
     __align__(16) uint32_t h[4096 * kI16Reps];  // coarse counts: h[bin * R + rep]
@@ -809,6 +813,13 @@ struct I16TileSmem {
     }
 };
 
+// Physical word of histogram word w = bin * R + replica: the 16-byte
+// chunks of each 64-word block are permuted by XOR with bits 6..9 of w, so
+// that the selection's 16-byte row reads (lane t reads words 16Rt ..
+// 16R(t+1) - 1) fall in distinct banks for 16 consecutive lanes; without it
+// lanes 64 or 128 bytes apart meet in the same few banks.
+__device__ __forceinline__ uint32_t i16_hidx(uint32_t w) { return w ^ (((w >> 6) & 15u) << 2); }
+
 // Coarse bin holding rank `need` (1-based) of the 4096-bin histogram h, and
 // the count of samples in lower bins, for the whole workgroup.  Thread t
 // sums bins 16t .. 16t+15 over the replicas; ends with a barrier after
@@ -818,11 +829,10 @@ __device__ __forceinline__ void i16_coarse_select(I16TileSmem& sm, uint32_t need
     constexpr int R = kI16Reps;
     const int tid = (int)threadIdx.x;
     const int lane = lane_id(), wave = tid >> 6;
-    const uint32_t* p = sm.h + tid * 16 * R;
     uint32_t c[16];
 #pragma unroll
     for (int j = 0; j < 16 * R; j += 4) {
-        const uint4 t = *reinterpret_cast<const uint4*>(p + j);
+        const uint4 t = *reinterpret_cast<const uint4*>(sm.h + i16_hidx((uint32_t)(tid * 16 * R + j)));
         const uint32_t w[4] = {t.x, t.y, t.z, t.w};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -894,13 +904,13 @@ __device__ void i16_tile_8192(const StreamView& d, int64_t first, uint64_t seed,
     if (tid == 0) sm.flagged = 0;
     __syncthreads();
 
-    uint32_t* hr = sm.h + (lane & (R - 1));
+    const uint32_t rep = (uint32_t)(lane & (R - 1));
     // Coarse digit of x + 32768: bits 4..15.
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const uint32_t u = v[q] ^ 0x80008000u;
-        atomicAdd(hr + ((u >> 4) & 0xFFFu) * R, 1u);
-        atomicAdd(hr + (u >> 20) * R, 1u);
+        atomicAdd(sm.h + i16_hidx(((u >> 4) & 0xFFFu) * R + rep), 1u);
+        atomicAdd(sm.h + i16_hidx((u >> 20) * R + rep), 1u);
         sched_fence();
     }
     __syncthreads();
@@ -933,8 +943,8 @@ __device__ void i16_tile_8192(const StreamView& d, int64_t first, uint64_t seed,
     // Coarse digit of |x - m| in [0, 65535].
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-        atomicAdd(hr + ((dd[q] >> 4) & 0xFFFu) * R, 1u);
-        atomicAdd(hr + (dd[q] >> 20) * R, 1u);
+        atomicAdd(sm.h + i16_hidx(((dd[q] >> 4) & 0xFFFu) * R + rep), 1u);
+        atomicAdd(sm.h + i16_hidx((dd[q] >> 20) * R + rep), 1u);
         sched_fence();
     }
     __syncthreads();
