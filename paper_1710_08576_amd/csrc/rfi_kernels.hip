@@ -806,6 +806,7 @@ struct I16TileSmem {
     uint32_t part[4];      // per-wave totals of the block scan
     int sel[2];            // selected coarse bin, count below it
     uint32_t flagged;
+    uint32_t mad_below;    // samples with |x - m| below the MAD bracket
     uint32_t noise_counts[4];
     __device__ NoiseScratch noise()
     {
@@ -823,9 +824,12 @@ __device__ __forceinline__ uint32_t i16_hidx(uint32_t w) { return w ^ (((w >> 6)
 // Coarse bin holding rank `need` (1-based) of the 4096-bin histogram h, and
 // the count of samples in lower bins, for the whole workgroup.  Thread t
 // sums bins 16t .. 16t+15 over the replicas; ends with a barrier after
-// which every thread may read sm.sel.
+// which every thread may read sm.sel, and h holds the inclusive cumulative
+// counts (h[bin] = samples in bins 0..bin; each thread rewrites only the
+// bins it read).
 __device__ __forceinline__ void i16_coarse_select(I16TileSmem& sm, uint32_t need)
 {
+    static_assert(kI16Reps == 1, "the cumulative counts are written one word per bin");
     constexpr int R = kI16Reps;
     const int tid = (int)threadIdx.x;
     const int lane = lane_id(), wave = tid >> 6;
@@ -862,7 +866,42 @@ __device__ __forceinline__ void i16_coarse_select(I16TileSmem& sm, uint32_t need
         sm.sel[0] = tid * 16 + cnt;
         sm.sel[1] = (int)below;
     }
+#pragma unroll
+    for (int j = 0; j < 16; j += 4)
+        *reinterpret_cast<uint4*>(sm.h + i16_hidx((uint32_t)(tid * 16 + j))) =
+            make_uint4(excl + c[j], excl + c[j + 1], excl + c[j + 2], excl + c[j + 3]);
     __syncthreads();
+}
+
+// Lower end of the MAD bracket from the cumulative coarse counts of x + 32768
+// (h after i16_coarse_select).  N(d) = #{|x - m| <= d} lies between the
+// counts of the coarse bins inside and touching [M - d, M + d] (M = m +
+// 32768); the smallest d whose touching count reaches `need` bounds the MAD
+// from below, and the MAD is at most 15 above it (every bin touching
+// [M - d, M + d] lies inside [M - d - 15, M + d + 15]).  A 64-way search by
+// each wave over d in [0, 65535] (three rounds); reads only, no barrier.
+__device__ __forceinline__ int i16_mad_lower(const I16TileSmem& sm, int M, uint32_t need)
+{
+    const int lane = lane_id();
+    int lo = 0, span = 65536;
+    while (span > 1) {
+        const int step = (span + 63) >> 6;
+        // sub-range `lane` is [lo + lane * step, lo + (lane + 1) * step - 1]
+        const int right = min(lo + (lane + 1) * step - 1, lo + span - 1);
+        bool ok = false;
+        if (lo + lane * step < lo + span) {
+            const int a = max(M - right, 0), c = min(M + right, 65535);
+            const uint32_t hiC = sm.h[i16_hidx((uint32_t)(c >> 4))];
+            const uint32_t loC = (a >> 4) > 0 ? sm.h[i16_hidx((uint32_t)((a >> 4) - 1))] : 0u;
+            ok = hiC - loC >= need;
+        }
+        const uint64_t b = __ballot(ok);  // the last sub-range always qualifies
+        const int f = (int)__builtin_ctzll(b);
+        const int nlo = lo + f * step;
+        span = min(step, lo + span - nlo);
+        lo = nlo;
+    }
+    return lo;
 }
 
 // Fine digit (0..15) holding rank `need` of the 16-bin histogram f; every
@@ -901,7 +940,10 @@ __device__ void i16_tile_8192(const StreamView& d, int64_t first, uint64_t seed,
     __syncthreads();  // the previous tile is done with the scratch
     zero_words(sm.h, 4096 * R, tid, kBlock);
     if (tid < 8) reinterpret_cast<uint4*>(&sm.fine[0][0])[tid] = make_uint4(0, 0, 0, 0);
-    if (tid == 0) sm.flagged = 0;
+    if (tid == 0) {
+        sm.flagged = 0;
+        sm.mad_below = 0;
+    }
     __syncthreads();
 
     const uint32_t rep = (uint32_t)(lane & (R - 1));
@@ -931,38 +973,30 @@ __device__ void i16_tile_8192(const StreamView& d, int64_t first, uint64_t seed,
             if (in1) atomicAdd(&sm.fine[0][(u >> 16) & 0xFu], 1u);
         }
     }
-    // The coarse counts are consumed: clear them for the |x - m| pass.
-    zero_words(sm.h, 4096 * R, tid, kBlock);
     __syncthreads();
     const int m = ((b1 << 4) | i16_fine_select(sm.fine[0], need - below1)) - 32768;
-    // |x - m| of both halves, kept for the fine pass.
+    // MAD: bracket [dlo, dlo + 15] from the coarse counts of x, then the
+    // exact rank inside it from |x - m| of the samples (no second histogram
+    // over 4096 bins).
+    const int dlo = i16_mad_lower(sm, m + 32768, need);
     const uint32_t m2 = rep_i16(m);
-    uint32_t dd[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) dd[q] = pk_absdiff_i16(v[q], m2);
-    // Coarse digit of |x - m| in [0, 65535].
+    uint32_t nbelow = 0;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-        atomicAdd(sm.h + i16_hidx(((dd[q] >> 4) & 0xFFFu) * R + rep), 1u);
-        atomicAdd(sm.h + i16_hidx((dd[q] >> 20) * R + rep), 1u);
-        sched_fence();
-    }
-    __syncthreads();
-    i16_coarse_select(sm, need);
-    const int b3 = sm.sel[0];
-    const uint32_t below3 = (uint32_t)sm.sel[1];
-    const uint32_t B3 = ((uint32_t)b3 << 4) | ((uint32_t)b3 << 20);
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const uint32_t t = dd[q] ^ B3;
-        const bool in0 = (t & 0xFFF0u) == 0, in1 = (t & 0xFFF00000u) == 0;
+        const uint32_t dq = pk_absdiff_i16(v[q], m2);
+        const uint32_t d0 = dq & 0xFFFFu, d1 = dq >> 16;
+        nbelow += (d0 < (uint32_t)dlo ? 1u : 0u) + (d1 < (uint32_t)dlo ? 1u : 0u);
+        const uint32_t r0 = d0 - (uint32_t)dlo, r1 = d1 - (uint32_t)dlo;  // wraps when below
+        const bool in0 = r0 < 16u, in1 = r1 < 16u;
         if (__ballot(in0 || in1) != 0) {
-            if (in0) atomicAdd(&sm.fine[1][dd[q] & 0xFu], 1u);
-            if (in1) atomicAdd(&sm.fine[1][(dd[q] >> 16) & 0xFu], 1u);
+            if (in0) atomicAdd(&sm.fine[1][r0], 1u);
+            if (in1) atomicAdd(&sm.fine[1][r1], 1u);
         }
     }
+    nbelow = group_sum<64>(nbelow);
+    if (lane == 63) atomicAdd(&sm.mad_below, nbelow);
     __syncthreads();
-    const int D = (b3 << 4) | i16_fine_select(sm.fine[1], need - below3);
+    const int D = dlo + i16_fine_select(sm.fine[1], need - sm.mad_below);
 
     float sig;
     const float t = threshold_of(D, d.k, sig);
