@@ -134,7 +134,8 @@ const char* rfi_status_string(int status);
  * Errors: RFI_ERR_INVALID (sizes, NULL with work to do, overlap),
  * RFI_ERR_ALIGN, RFI_ERR_NOMEM, RFI_ERR_HIP.  Asynchronous on `stream`.
  * Blocks of more than 64 KiB are summed in 64 KiB parts (a work buffer of
- * 8 bytes per part is kept by the library per lengths/block signature). */
+ * 8 bytes per part is kept by the library per lengths/block signature and
+ * stream, so calls on different streams do not share it). */
 int rfi_block_power(const void* x, int32_t elem_bytes, int32_t n_streams, const int64_t* lengths,
                     int32_t block, int64_t* power_out, void* stream);
 
@@ -183,7 +184,9 @@ int rfi_mad_filter_multi(const int8_t* x, int32_t n_out, int8_t* const* y, int32
  * (int)(1.4826f * M_m * 256.0f).  stats_out receives the window's median,
  * its own MAD, the flag count and t (it may be NULL).  Three passes over
  * the batch (statistics, median of MADs, replacement): the input is read
- * twice. */
+ * twice.  Work tables and temporaries (a few bytes per window) are kept by
+ * the library per argument signature and stream, so calls on different
+ * streams do not share them; rfi_shutdown frees them. */
 int rfi_mom_filter(const int8_t* x, int8_t* y, int32_t n_streams, const int64_t* lengths,
                    const int32_t* windows, const float* k, const int32_t* mode, int32_t mom_k,
                    uint64_t seed, rfi_window_stats* stats_out, void* stream);

@@ -7,7 +7,9 @@
 //      history (block counts + binary search over the 256 MAD values);
 //   3. Eqs. (1)-(2) with that value, which also rewrites each window's flag
 //      count and threshold.
-// Work tables and temporaries are kept per argument signature.
+// Work tables and temporaries are kept per argument signature and stream
+// (calls on one stream are ordered; calls on different streams use
+// different temporaries).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,6 +28,7 @@ int64_t align64(int64_t n) { return (n + 63) / 64 * 64; }
 
 struct MomKey {
     int device;
+    uintptr_t stream;  // temporaries are per stream: calls on one stream are ordered
     uint64_t seed;
     std::vector<int64_t> L;
     std::vector<int32_t> W;
@@ -34,6 +37,7 @@ struct MomKey {
     bool operator<(const MomKey& o) const
     {
         if (device != o.device) return device < o.device;
+        if (stream != o.stream) return stream < o.stream;
         if (seed != o.seed) return seed < o.seed;
         if (L != o.L) return L < o.L;
         if (W != o.W) return W < o.W;
@@ -198,6 +202,7 @@ int rfi_mom_filter(const int8_t* x, int8_t* y, int32_t n_streams, const int64_t*
     if (n_streams == 0 || total == 0) return RFI_OK;
     MomKey key;
     if (hipGetDevice(&key.device) != hipSuccess) key.device = 0;
+    key.stream = (uintptr_t)stream;
     key.seed = seed;
     key.L.assign(lengths, lengths + n_streams);
     key.W.assign(windows, windows + n_streams);

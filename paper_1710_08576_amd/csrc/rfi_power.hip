@@ -16,7 +16,7 @@
 // 16-B loads (int8: v_dot4 of each word with itself; int16: v_dot2 of the
 // absolute values), so a large block is spread over many workgroups; the
 // parts of a block are then added by a second small kernel.  Work tables
-// are kept per (lengths, block) signature.
+// are kept per (lengths, block) signature and stream.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -234,12 +234,14 @@ __global__ __launch_bounds__(kPowBlock) void k_improvement(const PowRow* rows, i
 // ---------------------------------------------------------------------------
 struct PowKey {
     int device;
-    int elem;  // 0: improvement only (no parts)
+    uintptr_t stream;  // the parts buffer is per stream: calls on one stream are ordered
+    int elem;          // 0: improvement only (no parts)
     int32_t block;
     std::vector<int64_t> L;
     bool operator<(const PowKey& o) const
     {
         if (device != o.device) return device < o.device;
+        if (stream != o.stream) return stream < o.stream;
         if (elem != o.elem) return elem < o.elem;
         if (block != o.block) return block < o.block;
         return L < o.L;
@@ -290,10 +292,11 @@ bool pow_rows(int elem, int32_t n, const int64_t* L, int32_t block, std::vector<
     return true;
 }
 
-int pow_plan(int elem, int32_t n, const int64_t* L, int32_t block, PowPlan** out)
+int pow_plan(int elem, int32_t n, const int64_t* L, int32_t block, hipStream_t stream, PowPlan** out)
 {
     PowKey key;
     if (hipGetDevice(&key.device) != hipSuccess) key.device = 0;
+    key.stream = (uintptr_t)stream;
     key.elem = elem;
     key.block = block;
     key.L.assign(L, L + n);
@@ -371,7 +374,7 @@ int rfi_block_power(const void* x, int32_t elem_bytes, int32_t n_streams, const 
     if (pa < xa + xb && xa < pa + pb) return RFI_ERR_INVALID;
     std::lock_guard<std::mutex> g(g_pow_mu);
     PowPlan* p = nullptr;
-    int rc = pow_plan(elem_bytes, n_streams, lengths, block, &p);
+    int rc = pow_plan(elem_bytes, n_streams, lengths, block, (hipStream_t)stream, &p);
     if (rc != RFI_OK) return rc;
     hipStream_t s = (hipStream_t)stream;
     const int direct = p->ppb == 1 ? 1 : 0;
@@ -414,7 +417,7 @@ int rfi_improvement(const int64_t* power_u, const int64_t* power_f, int32_t n_st
     }
     std::lock_guard<std::mutex> g(g_pow_mu);
     PowPlan* p = nullptr;
-    int rc = pow_plan(0, n_streams, lengths, block, &p);
+    int rc = pow_plan(0, n_streams, lengths, block, (hipStream_t)stream, &p);
     if (rc != RFI_OK) return rc;
     hipLaunchKernelGGL(k_improvement, dim3((unsigned)n_streams), dim3(kPowBlock), 0, (hipStream_t)stream,
                        p->d_rows, (int64_t)block, seg_blocks, power_u, power_f, out);

@@ -166,3 +166,24 @@ def test_breakdown_on_emulator_bursts_matches_oracle(gpu, on):
         assert det_mad > 0.9 * det_mom
     elif on >= 51200:
         assert det_mad < 0.15 * det_mom
+
+
+def test_block_power_two_streams_same_signature(gpu):
+    # blocks of 3 * 2^20 go through the parts buffer, which is per stream
+    lengths, block = [5_000_000, 3_000_001], 3 << 20
+    xa = _packed(lengths, np.int8, 501)
+    xb = _packed(lengths, np.int8, 502)
+    da, db = torch.from_numpy(xa).to(gpu), torch.from_numpy(xb).to(gpu)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    nb = rfi.n_blocks(lengths, block)
+    pa = torch.empty(nb, dtype=torch.int64, device=gpu)
+    pb = torch.empty(nb, dtype=torch.int64, device=gpu)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        with torch.cuda.stream(s1):
+            rfi.block_power(da, lengths, block, out=pa, stream=s1)
+        with torch.cuda.stream(s2):
+            rfi.block_power(db, lengths, block, out=pb, stream=s2)
+    torch.cuda.synchronize()
+    assert np.array_equal(pa.cpu().numpy(), oracle.block_power(xa, lengths, block))
+    assert np.array_equal(pb.cpu().numpy(), oracle.block_power(xb, lengths, block))

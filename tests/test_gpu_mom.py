@@ -121,3 +121,23 @@ def test_arg_errors(gpu):
     assert e.value.status == -1
     with pytest.raises(rfi.RfiError):
         rfi.mom_filter(xd, [4096], [0], [3.0], [1], 4)
+
+
+def test_two_streams_same_signature(gpu):
+    # the same argument signature on two HIP streams at once: each call has
+    # its own temporaries, so both results equal the oracle's
+    specs = [synth.StreamSpec(4096 * 300 + 77, 4096, 3.0, m, 8.0 + 3 * m, 0.01, 8, 3000) for m in (0, 1, 2)]
+    xa, L, W, K, M = _batch(specs, 901)
+    xb, _, _, _, _ = _batch(specs, 902)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    da, db = torch.from_numpy(xa).to(gpu), torch.from_numpy(xb).to(gpu)
+    ya, yb = torch.empty_like(da), torch.empty_like(db)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        with torch.cuda.stream(s1):
+            _, sta = rfi.mom_filter(da, L, W, K, M, 64, seed=4, y=ya, stream=s1)
+        with torch.cuda.stream(s2):
+            _, stb = rfi.mom_filter(db, L, W, K, M, 64, seed=4, y=yb, stream=s2)
+    torch.cuda.synchronize()
+    _check(xa, L, W, K, M, 64, 4, ya.cpu().numpy(), rfi.stats_numpy(sta), padding=False)
+    _check(xb, L, W, K, M, 64, 4, yb.cpu().numpy(), rfi.stats_numpy(stb), padding=False)
