@@ -163,3 +163,47 @@ def test_full_size_sampled(gpu):
             assert stn[p] == sto, (W, mode, s, w)
         del x, y, st
         torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("elem,sched", [(1, "fused"), (1, "split_concurrent"), (1, "fused_persist"), (2, "fused")])
+def test_graph_replays_each_checked(gpu, elem, sched):
+    """A captured plan replayed four times, with eager work between the
+    replays (the input changed in place, outputs cleared, synchronisations):
+    every replay equals an eager run on the same input."""
+    if elem == 1:
+        specs = synth.batching(n_streams=12, lo=1 << 14, hi=1 << 16, seed=6)
+        specs += [synth.StreamSpec(40000, 3000, 3.0, rfi.NOISE, 10.0, 0.01, 8, 64)]
+    else:
+        specs = [synth.StreamSpec(8192 * 9 + 500, 8192, 3.0, m, 400.0, 0.01, 32, 32, "i16") for m in (0, 1, 2)]
+    x0 = synth.gen_packed(specs, seed=6, tag=6)
+    L, W, K, M = unpack(specs)
+    xd = x0.to(gpu)
+    so, _, nw, _ = rfi.layout(L, W)
+    g = rfi.Plan(elem, L, W, K, M, seed=3)
+    g.set_schedule(sched)
+    g.set_graph(True)
+    e = rfi.Plan(elem, L, W, K, M, seed=3)
+    yd = torch.empty_like(xd)
+    st = torch.empty((nw, 4), dtype=torch.int32, device=gpu)
+    ye = torch.empty_like(xd)
+    ste = torch.empty((nw, 4), dtype=torch.int32, device=gpu)
+    stream = torch.cuda.Stream()
+    for i in range(4):
+        if i > 0:  # eager work on the default stream between replays
+            xd[i::97] = (xd[i::97].to(torch.int32) * 3 - 7).clamp(-128 if elem == 1 else -32768,
+                                                                   127 if elem == 1 else 32767).to(xd.dtype)
+        yd.fill_(0x5A if elem == 1 else 0x5A5A)
+        st.fill_(-1)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            g.execute(xd, yd, st, stream=stream)
+        stream.synchronize()
+        e.execute(xd, ye, ste)
+        torch.cuda.synchronize()
+        a, b = yd.cpu().numpy(), ye.cpu().numpy()
+        for o, n in zip(so, L):
+            assert np.array_equal(a[o:o + n], b[o:o + n]), (sched, i)
+        assert torch.equal(st, ste), (sched, i)
+    check_against_oracle(xd.cpu(), specs, 3, yd.cpu().numpy(), rfi.stats_numpy(st), check_padding=False)
+    g.close()
+    e.close()
