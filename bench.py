@@ -83,6 +83,7 @@ def main():
     ap.add_argument("--no-multi", action="store_true")
     ap.add_argument("--no-analysis", action="store_true",
                     help="skip the improvement-metric and MAD-breakdown sections")
+    ap.add_argument("--no-lds", action="store_true", help="skip the LDS histogram-rate microbenchmark")
     ap.add_argument("--serve-blocks", type=int, default=10000,
                     help="blocks per stream in the real-time serving replay")
     ap.add_argument("--with-copy", action="store_true",
@@ -224,6 +225,8 @@ def main():
     if not args.no_analysis:
         out["improvement_metric"] = bench_improvement(args, dev, x, y, L)
         out["mad_breakdown"] = bench_breakdown(args, dev)
+    if not args.no_lds:
+        out["lds_atomic_rate"] = bench_lds(args, dev, x)
     if not args.no_serving:
         del x, y
         torch.cuda.empty_cache()
@@ -475,6 +478,47 @@ def bench_breakdown(args, dev):
             row[name] = {"detected": round(det, 4), "ms": round(ms, 4)}
         out[f"on_{on}"] = row
         del x, yb
+    return out
+
+
+CU_COUNT, CLOCK_GHZ = 256, 2.4
+
+
+def bench_lds(args, dev, x):
+    """The int8 selection's second roof: LDS atomics per CU per clock of the
+    histogram microbenchmark (one atomic per sample, per-wave histograms of
+    R replicas), on the plain-scale bytes for R = 1, 2, 4, 8 and on Gaussian
+    int8 of several sigma at R = 4 (the tile kernels' choice).  At 70 % of
+    8 TB/s the int8 filter needs 2.8 Gsamples/s = 4.6 atomics per CU per
+    clock."""
+    import torch
+
+    from paper_1710_08576_amd import _lib
+    stream = torch.cuda.current_stream()
+    hist = torch.zeros((256, 256), dtype=torch.int32, device=dev)
+    n = x.numel() // 16384 * 16384
+    xs = x[:n]
+
+    def rate(buf, r):
+        for _ in range(2):
+            _lib.ubench_lds_hist(buf, r, hist=hist)
+        ms = _time_events(lambda: _lib.ubench_lds_hist(buf, r, hist=hist), 10, stream)
+        return {"ms": round(ms, 4), "atomics_per_cu_clock": round(buf.numel() / (ms * 1e-3) / (CU_COUNT * CLOCK_GHZ * 1e9), 2)}
+
+    out = {"unit": "lane-atomics per CU per clock (256 CUs, 2.4 GHz)", "needed_at_70pct": 4.56,
+           "plain_scale": {f"R{r}": rate(xs, r) for r in (1, 2, 4, 8)}}
+    g = torch.Generator(device=dev)
+    g.manual_seed(5)
+    m = 1 << 28
+    sweep = {}
+    for sigma in (2, 6, 20, 60):
+        buf = torch.clamp(torch.round(torch.randn(m, generator=g, device=dev) * sigma), -128, 127).to(torch.int8)
+        sweep[f"sigma_{sigma}"] = rate(buf, 4)
+        del buf
+    buf = torch.randint(-128, 128, (m,), generator=g, dtype=torch.int8, device=dev)
+    sweep["uniform"] = rate(buf, 4)
+    del buf
+    out["gaussian_R4"] = sweep
     return out
 
 

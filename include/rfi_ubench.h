@@ -17,6 +17,21 @@
  *               rotated order (t + g) mod 4.
  *   stream   hipStream_t (NULL = null stream).
  * Returns 0, RFI_ERR_INVALID (-1) or RFI_ERR_ALIGN (-2); asynchronous.
+ *
+ * rfi_ubench_lds_hist: the LDS atomic rate of the int8 selection's
+ * histogram, the filter's second roof after HBM.  Each workgroup reads a
+ * 16 KiB tile of x in the filter's load shape and counts every byte into
+ * per-wave LDS histograms of `replicas` copies (replica = lane % replicas),
+ * one LDS atomic per byte; the counts of workgroup g are then added to row
+ * g % 256 of hist_out.
+ *   x          device, 16-byte aligned, bytes a multiple of 16384; bins are
+ *              raw byte values 0..255.
+ *   replicas   1, 2, 4 or 8.
+ *   hist_out   device uint32[256 * 256] (row-major, 256 rows of 256 bins),
+ *              4-byte aligned, accumulated into (the caller clears it
+ *              first); the byte counts are the column sums.
+ * Returns 0, RFI_ERR_INVALID (-1), RFI_ERR_ALIGN (-2) or RFI_ERR_HIP (-5);
+ * asynchronous on stream.
  */
 #ifndef RFI_UBENCH_H
 #define RFI_UBENCH_H
@@ -29,6 +44,7 @@ extern "C" {
 #endif
 
 int rfi_ubench_copy(const void* x, void* y, uint64_t bytes, int32_t variant, void* stream);
+int rfi_ubench_lds_hist(const void* x, uint64_t bytes, int32_t replicas, uint32_t* hist_out, void* stream);
 
 #ifdef __cplusplus
 }

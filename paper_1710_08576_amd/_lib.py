@@ -84,6 +84,7 @@ _SIGS = {
     "rfi_server_replay": (ctypes.c_int, [P, I64, P, P, P, P, P, P, P, P]),
     "rfi_server_destroy": (ctypes.c_int, [P]),
     "rfi_ubench_copy": (ctypes.c_int, [P, P, U64, I32, P]),
+    "rfi_ubench_lds_hist": (ctypes.c_int, [P, U64, I32, P, P]),
 }
 
 
@@ -163,6 +164,20 @@ def ubench_copy(x, y, variant=0, stream=None):
     nbytes = x.numel() * x.element_size()
     _check(load().rfi_ubench_copy(_tptr(x), _tptr(y), nbytes, variant, _stream_handle(stream)),
            "rfi_ubench_copy")
+
+
+def ubench_lds_hist(x, replicas=4, hist=None, stream=None):
+    """LDS histogram-rate microbenchmark: counts the bytes of x (a multiple
+    of 16 KiB) into per-wave LDS histograms with `replicas` copies; returns
+    the int32 [256, 256] tensor (uint32 counts) it added to, whose column
+    sums are the 256 raw-byte counts."""
+    import torch
+    nbytes = x.numel() * x.element_size()
+    if hist is None:
+        hist = torch.zeros((256, 256), dtype=torch.int32, device=x.device)
+    _check(load().rfi_ubench_lds_hist(_tptr(x), nbytes, int(replicas), _tptr(hist), _stream_handle(stream)),
+           "rfi_ubench_lds_hist")
+    return hist
 
 
 def stats_numpy(stats_t) -> np.ndarray:

@@ -61,7 +61,68 @@ __global__ __launch_bounds__(256) void k_copy_stride(const uint8_t* __restrict__
         gstore16(y + i * 16, gload16(x + i * 16));
 }
 
+// LDS histogram rate: each workgroup loads a 16 KiB tile in the filter's
+// shape (64 B per lane, four 16-byte loads at a 1 KiB stride) and counts its
+// bytes into per-wave LDS histograms of R replicas (replica = lane % R,
+// 264-word stride, as the int8 tile kernels do), one LDS atomic per sample;
+// the workgroup's totals are then added to row (workgroup % 256) of a
+// 256 x 256 global array (spreading the global atomics over rows keeps
+// their contention out of the measurement).
+template <int R>
+__global__ __launch_bounds__(256) void k_lds_hist(const uint8_t* __restrict__ x, uint32_t* __restrict__ out)
+{
+    constexpr int kStride = 264;
+    __shared__ __align__(16) uint32_t h[4 * R * kStride];
+    const int lane = lane_id(), wave = (int)(threadIdx.x >> 6);
+    uint32_t* hw = h + wave * R * kStride;
+    for (int j = lane * 4; j < R * kStride; j += 256) *reinterpret_cast<uint4*>(hw + j) = make_uint4(0, 0, 0, 0);
+    const uint8_t* xt = x + (size_t)blockIdx.x * 16384 + wave * 4096 + lane * 16;
+    uint32_t v[16];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint4 t = gload16_nt(xt + i * 1024);
+        v[4 * i] = t.x;
+        v[4 * i + 1] = t.y;
+        v[4 * i + 2] = t.z;
+        v[4 * i + 3] = t.w;
+    }
+    wave_sync();
+    uint32_t* hl = hw + (lane % R) * kStride;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        atomicAdd(hl + (v[q] & 0xFFu), 1u);
+        atomicAdd(hl + ((v[q] >> 8) & 0xFFu), 1u);
+        atomicAdd(hl + ((v[q] >> 16) & 0xFFu), 1u);
+        atomicAdd(hl + (v[q] >> 24), 1u);
+        sched_fence();
+    }
+    __syncthreads();
+    const int bin = (int)threadIdx.x;
+    uint32_t t = 0;
+    for (int w = 0; w < 4; ++w)
+        for (int r = 0; r < R; ++r) t += h[(w * R + r) * kStride + bin];
+    if (t) atomicAdd(out + (blockIdx.x & 255u) * 256u + bin, t);
+}
+
 }  // namespace rfi
+
+extern "C" int rfi_ubench_lds_hist(const void* x, uint64_t bytes, int32_t replicas, uint32_t* hist_out,
+                                   void* stream)
+{
+    if (!x || !hist_out || bytes == 0 || bytes % 16384 != 0) return -1;
+    if (replicas != 1 && replicas != 2 && replicas != 4 && replicas != 8) return -1;
+    if (((uintptr_t)x & 15u) || ((uintptr_t)hist_out & 3u)) return -2;
+    const uint64_t tiles = bytes / 16384;
+    if (tiles > (1u << 30)) return -1;
+    const uint8_t* xs = static_cast<const uint8_t*>(x);
+    hipStream_t s = (hipStream_t)stream;
+    const dim3 g((unsigned)tiles), b(256);
+    if (replicas == 1) hipLaunchKernelGGL(rfi::k_lds_hist<1>, g, b, 0, s, xs, hist_out);
+    else if (replicas == 2) hipLaunchKernelGGL(rfi::k_lds_hist<2>, g, b, 0, s, xs, hist_out);
+    else if (replicas == 4) hipLaunchKernelGGL(rfi::k_lds_hist<4>, g, b, 0, s, xs, hist_out);
+    else hipLaunchKernelGGL(rfi::k_lds_hist<8>, g, b, 0, s, xs, hist_out);
+    return hipGetLastError() == hipSuccess ? 0 : -5;
+}
 
 extern "C" int rfi_ubench_copy(const void* x, void* y, uint64_t bytes, int32_t variant, void* stream)
 {
