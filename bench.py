@@ -155,7 +155,8 @@ def main():
     # one 16 KiB tile per workgroup.
     cls = {512: 0, 1024: 1, 2048: 2, 4096: 3, 8192: 4, 16384: 5}[args.window]
     traffic, traffic_src = measured_traffic("k_i8_tiles<%d, %d, false, 1>" % (cls, 1 << dom))
-    modes = {MODE_NAMES[m]: {"ms": round(per_mode_ms[m], 4),
+    med_ms = {m: float(np.median([a.elapsed_time(b) for a, b in zip(*events[m])])) for m in (0, 1, 2)}
+    modes = {MODE_NAMES[m]: {"ms": round(per_mode_ms[m], 4), "ms_median": round(med_ms[m], 4),
                              "gsamples_s": round(n_samples / per_mode_ms[m] / 1e6, 1),
                              "gb_s": round(abytes / per_mode_ms[m] / 1e6, 1),
                              "launches": launches[m]}
@@ -267,7 +268,9 @@ def _cpu_model():
 
 
 def _time_events(fn, iters, stream):
-    """Mean ms of fn() over iters runs, HIP events on `stream`."""
+    """Median ms of fn() over iters runs, HIP events on `stream` (the
+    median: a rare stall of tens of milliseconds on the box would otherwise
+    dominate a mean over ten runs)."""
     import numpy as np
     import torch
     evs = []
@@ -278,7 +281,7 @@ def _time_events(fn, iters, stream):
         b.record(stream)
         evs.append((a, b))
     torch.cuda.synchronize()
-    return float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    return float(np.median([a.elapsed_time(b) for a, b in evs]))
 
 
 def bench_batching(args, dev):
