@@ -42,8 +42,12 @@
  * arrays (lengths, windows, k, mode) are read during the call only.  All
  * work is asynchronous on `stream` (a hipStream_t; NULL = the null stream).
  * y == x (exactly in place) is allowed; any other overlap is rejected.
- * Errors: every entry point returns an rfi_status; nothing is enqueued when
- * it is not RFI_OK.  Device faults surface at the caller's synchronisation.
+ * Errors: every entry point returns an rfi_status.  Argument errors
+ * (RFI_ERR_INVALID, RFI_ERR_ALIGN, RFI_ERR_UNSUPPORTED) are found before
+ * anything is enqueued; after RFI_ERR_NOMEM or RFI_ERR_HIP from a call that
+ * runs several passes, earlier passes may already be enqueued and the
+ * outputs are undefined.  Device faults surface at the caller's
+ * synchronisation.
  */
 #ifndef RFI_MAD_H
 #define RFI_MAD_H
