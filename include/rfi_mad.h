@@ -195,6 +195,29 @@ int rfi_mom_filter(const int8_t* x, int8_t* y, int32_t n_streams, const int64_t*
                    const int32_t* windows, const float* k, const int32_t* mode, int32_t mom_k,
                    uint64_t seed, rfi_window_stats* stats_out, void* stream);
 
+/* Median of MAD carried across calls, for streams that arrive in pieces
+ * (real-time use): as rfi_mom_filter, plus per stream the MADs of its
+ * earlier windows and the absolute index of its first sample, so that a
+ * stream cut at window boundaries into consecutive calls gives the same
+ * output and statistics as one rfi_mom_filter call over the whole stream
+ * (a short final window only in the last piece).
+ *   abs_base     device int64[n_streams] (8-byte aligned) or NULL (all 0):
+ *                absolute index of each stream's first sample in this
+ *                call (drives the noise counter).
+ *   mad_history  device uint8[n_streams * (mom_k - 1)]: per stream the MADs
+ *                of its latest earlier windows, right-aligned (slot
+ *                mom_k - 2 holds the most recent), in and out.
+ *   history_len  device int32[n_streams] (4-byte aligned): how many slots
+ *                hold valid MADs (0 for a new stream, at most mom_k - 1;
+ *                clamped to that range), in and out.
+ * With mom_k == 1 neither history argument is used (they may be NULL).
+ * Errors as rfi_mom_filter; RFI_ERR_INVALID also for NULL history arrays
+ * when mom_k > 1.  Work buffers are kept per signature, mom_k and stream. */
+int rfi_mom_filter_carry(const int8_t* x, int8_t* y, int32_t n_streams, const int64_t* lengths,
+                         const int32_t* windows, const float* k, const int32_t* mode, int32_t mom_k,
+                         uint64_t seed, const int64_t* abs_base, uint8_t* mad_history, int32_t* history_len,
+                         rfi_window_stats* stats_out, void* stream);
+
 /* ------------------------------------------------------------------ */
 /* Explicit plans: a work table for one argument signature, reusable   */
 /* across calls, with a selectable launch schedule and HIP-graph       */

@@ -53,6 +53,7 @@ _SIGS = {
     "rfi_mad_filter": (ctypes.c_int, [P, P, I32, P, P, P, P, U64, P, P]),
     "rfi_mad_filter_i16": (ctypes.c_int, [P, P, I32, P, P, P, P, U64, P, P]),
     "rfi_mom_filter": (ctypes.c_int, [P, P, I32, P, P, P, P, I32, U64, P, P]),
+    "rfi_mom_filter_carry": (ctypes.c_int, [P, P, I32, P, P, P, P, I32, U64, P, P, P, P, P]),
     "rfi_mad_filter_multi": (ctypes.c_int, [P, I32, P, I32, P, P, P, P, U64, P, P]),
     "rfi_block_power": (ctypes.c_int, [P, I32, I32, P, I32, P, P]),
     "rfi_improvement": (ctypes.c_int, [P, P, I32, P, I32, I32, P, P]),
@@ -253,6 +254,28 @@ def mom_filter(x, lengths, windows, k, mode, mom_k: int, seed: int = 0, y=None, 
     rc = load().rfi_mom_filter(_tptr(x), _tptr(y), n, _ptr(L), _ptr(W), _ptr(K), _ptr(M), int(mom_k),
                                seed, _tptr(st), _stream_handle(stream))
     _check(rc, "rfi_mom_filter")
+    return y, (st[:nw] if st is not None else None)
+
+
+def mom_filter_carry(x, lengths, windows, k, mode, mom_k: int, abs_base, history, history_len, seed: int = 0,
+                     y=None, stats=True, stream=None):
+    """Median-of-MAD filter carried across calls: abs_base (int64 [n]),
+    history (uint8 [n, mom_k - 1]) and history_len (int32 [n]) are CUDA
+    tensors; history and history_len are updated in place."""
+    import torch
+    n = len(lengths)
+    L = np.ascontiguousarray(lengths, dtype=np.int64)
+    W, K, M = _arr(windows, np.int32, n), _arr(k, np.float32, n), _arr(mode, np.int32, n)
+    _, _, nw, _ = layout(L, W)
+    if x.dtype != torch.int8:
+        raise TypeError("x must be int8")
+    if y is None:
+        y = torch.empty_like(x)
+    st = torch.empty((max(nw, 1), 4), dtype=torch.int32, device=x.device) if stats else None
+    rc = load().rfi_mom_filter_carry(_tptr(x), _tptr(y), n, _ptr(L), _ptr(W), _ptr(K), _ptr(M), int(mom_k), seed,
+                                     _tptr(abs_base), _tptr(history), _tptr(history_len), _tptr(st),
+                                     _stream_handle(stream))
+    _check(rc, "rfi_mom_filter_carry")
     return y, (st[:nw] if st is not None else None)
 
 

@@ -144,20 +144,34 @@ hipError_t launch_i8_multi(int cls, const MultiArgs& ma, int grid, hipStream_t s
 
 // Median of MAD (int8).  Windows of all streams are numbered globally in
 // the packed stats order; mad[g] is window g's own MAD, dm[g] receives the
-// lower median of the MADs of its stream's windows max(0, w-K+1) .. w.
+// lower median of the MADs of its stream's last K windows.  Each stream's
+// MAD sequence (emad, from eoff) is `pre` history slots (the MADs of earlier
+// calls, right-aligned, hist_len[s] of them valid) followed by its windows;
+// pre = 0 when there is no history, and emad is mad itself.
 struct MomStream {
-    int64_t woff;   // first global window index of the stream
-    int64_t nw;     // windows of the stream
+    int64_t woff;   // first window of the stream in the stats order
+    int64_t nw;     // windows of the stream in this call
+    int64_t eoff;   // first entry of the stream's MAD sequence
+    int64_t pre;    // history slots before its first window (0 or K - 1)
     int64_t hoff;   // first row of the stream's block-count table
 };
-constexpr int kMomBlock = 64;  // windows per row of the block-count table
-// hcnt[(hoff + b) * 256 + v] = #{j < 64 b : mad_j <= v} of the stream.
-// max_blocks: the largest ceil(nw / 64) over the streams.
+constexpr int kMomBlock = 64;  // entries per row of the block-count table
+// hcnt[(hoff + b) * 256 + v] = #{j < 64 b : emad_j <= v} over the stream's
+// sequence (pre + nw entries).  max_blocks: the largest ceil((pre + nw) / 64).
 hipError_t launch_mom_counts(const MomStream* streams, int n_streams, int64_t max_blocks,
-                             const uint8_t* mad, uint32_t* hcnt, hipStream_t s);
+                             const uint8_t* emad, uint32_t* hcnt, hipStream_t s);
+// hist_len: NULL when no stream has history slots.
 hipError_t launch_mom_select(const MomStream* streams, int n_streams, int64_t total_windows,
-                             int32_t mom_k, const uint8_t* mad, const uint32_t* hcnt, int32_t* dm,
-                             hipStream_t s);
+                             int32_t mom_k, const uint8_t* emad, const uint32_t* hcnt,
+                             const int32_t* hist_len, int32_t* dm, hipStream_t s);
+// emad of streams with history slots: hist[s * pre + i] for the slots, then
+// mad[woff + w] (total_ext = sum of pre + nw).
+hipError_t launch_mom_extend(const MomStream* streams, int n_streams, int64_t total_ext,
+                             const uint8_t* mad, const uint8_t* hist, uint8_t* emad, hipStream_t s);
+// New history: the last min(pre, hist_len + nw) entries of each stream's
+// sequence, right-aligned in hist[s * pre ..], and hist_len updated.
+hipError_t launch_mom_history(const MomStream* streams, int n_streams, const uint8_t* emad, uint8_t* hist,
+                              int32_t* hist_len, hipStream_t s);
 // Replacement pass: items of up to 256 windows (<= 16 KiB) of one stream;
 // window params from stats (median) and dm; rewrites n_flagged and threshold.
 struct MomItem {
@@ -165,9 +179,10 @@ struct MomItem {
     int32_t n_windows;
     int64_t first_window;  // within the stream
 };
+// abs_add: NULL, or per stream an offset added to its absolute sample index.
 hipError_t launch_mom_apply(const LaunchArgs& a, const MomItem* items, int64_t n_items,
-                            const int32_t* dm, const int64_t* stream_woff, rfi_window_stats* stats,
-                            hipStream_t s);
+                            const int32_t* dm, const int64_t* stream_woff, const int64_t* abs_add,
+                            rfi_window_stats* stats, hipStream_t s);
 // Copies the MAD of every window out of the stats array (int8 MADs fit a byte).
 hipError_t launch_mom_gather(const rfi_window_stats* stats, int64_t total_windows, uint8_t* mad,
                              hipStream_t s);

@@ -1443,11 +1443,12 @@ __global__ __launch_bounds__(256) void k_mom_block_counts(const MomStream* __res
                                                           uint32_t* __restrict__ hcnt)
 {
     const MomStream st = streams[blockIdx.y];
+    const int64_t n = st.pre + st.nw;
     const int64_t j0 = (int64_t)blockIdx.x * kMomBlock;
-    if (j0 >= st.nw) return;
+    if (j0 >= n) return;
     __shared__ uint8_t m[kMomBlock];
-    const int64_t j1 = min(j0 + kMomBlock, st.nw);
-    if ((int64_t)threadIdx.x < j1 - j0) m[threadIdx.x] = mad[st.woff + j0 + threadIdx.x];
+    const int64_t j1 = min(j0 + kMomBlock, n);
+    if ((int64_t)threadIdx.x < j1 - j0) m[threadIdx.x] = mad[st.eoff + j0 + threadIdx.x];
     __syncthreads();
     const uint32_t v = threadIdx.x;
     uint32_t c = 0;
@@ -1460,7 +1461,7 @@ __global__ __launch_bounds__(256) void k_mom_counts(const MomStream* __restrict_
 {
     const MomStream st = streams[blockIdx.x];
     uint32_t* row = hcnt + st.hoff * 256 + threadIdx.x;
-    const int64_t nb = (st.nw + kMomBlock - 1) / kMomBlock;
+    const int64_t nb = (st.pre + st.nw + kMomBlock - 1) / kMomBlock;
     uint32_t run = 0;
     row[0] = 0;
     for (int64_t b = 1; b <= nb; ++b) {
@@ -1482,6 +1483,7 @@ __global__ __launch_bounds__(kBlock) void k_mom_select(const MomStream* __restri
                                                        int64_t total, int32_t K,
                                                        const uint8_t* __restrict__ mad,
                                                        const uint32_t* __restrict__ hcnt,
+                                                       const int32_t* __restrict__ hist_len,
                                                        int32_t* __restrict__ dm)
 {
     const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -1494,9 +1496,12 @@ __global__ __launch_bounds__(kBlock) void k_mom_select(const MomStream* __restri
     }
     const MomStream st = streams[lo_s];
     const int64_t w = g - st.woff;
-    const int64_t a = w + 1 > K ? w + 1 - K : 0, b = w + 1;
+    // sequence position of window w; the valid history starts pre - H back
+    const int64_t p = st.pre + w;
+    const int64_t H = st.pre > 0 ? min(max((int64_t)hist_len[lo_s], (int64_t)0), st.pre) : 0;
+    const int64_t a = max(st.pre - H, p + 1 - (int64_t)K), b = p + 1;
     const uint32_t need = (uint32_t)((b - a - 1) / 2 + 1);
-    const uint8_t* m = mad + st.woff;
+    const uint8_t* m = mad + st.eoff;
     const uint32_t* h = hcnt + st.hoff * 256;
     int lo = 0, hi = 255;  // smallest v with #{a <= j < b : mad_j <= v} >= need
     while (lo < hi) {
@@ -1505,6 +1510,42 @@ __global__ __launch_bounds__(kBlock) void k_mom_select(const MomStream* __restri
         else lo = mid + 1;
     }
     dm[g] = lo;
+}
+
+// emad of streams with history slots (see launch_mom_extend).
+__global__ __launch_bounds__(kBlock) void k_mom_extend(const MomStream* __restrict__ streams, int n_streams,
+                                                       int64_t total_ext, const uint8_t* __restrict__ mad,
+                                                       const uint8_t* __restrict__ hist,
+                                                       uint8_t* __restrict__ emad)
+{
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= total_ext) return;
+    int lo_s = 0, hi_s = n_streams - 1;  // last stream with eoff <= q
+    while (lo_s < hi_s) {
+        const int mid = (lo_s + hi_s + 1) / 2;
+        if (streams[mid].eoff <= q) lo_s = mid;
+        else hi_s = mid - 1;
+    }
+    const MomStream st = streams[lo_s];
+    const int64_t i = q - st.eoff;
+    emad[q] = i < st.pre ? hist[lo_s * st.pre + i] : mad[st.woff + (i - st.pre)];
+}
+
+// One workgroup per stream: the new right-aligned history, then its length.
+__global__ __launch_bounds__(kBlock) void k_mom_history(const MomStream* __restrict__ streams,
+                                                        const uint8_t* __restrict__ emad,
+                                                        uint8_t* __restrict__ hist,
+                                                        int32_t* __restrict__ hist_len)
+{
+    const MomStream st = streams[blockIdx.x];
+    if (st.pre == 0) return;
+    const int64_t H = min(max((int64_t)hist_len[blockIdx.x], (int64_t)0), st.pre);
+    const int64_t Hn = min(st.pre, H + st.nw);
+    // slot i (i >= pre - Hn) takes sequence entry nw + i
+    for (int64_t i = st.pre - Hn + threadIdx.x; i < st.pre; i += kBlock)
+        hist[blockIdx.x * st.pre + i] = emad[st.eoff + st.nw + i];
+    __syncthreads();  // every thread has read hist_len
+    if (threadIdx.x == 0) hist_len[blockIdx.x] = (int32_t)Hn;
 }
 
 struct MomSmem {
@@ -1758,11 +1799,13 @@ hipError_t launch_i16_fused(const LaunchArgs& a, int grid, hipStream_t s)
 __global__ __launch_bounds__(kBlock) void k_mom_apply(LaunchArgs a, const MomItem* __restrict__ items,
                                                       const int32_t* __restrict__ dm,
                                                       const int64_t* __restrict__ stream_woff,
+                                                      const int64_t* __restrict__ abs_add,
                                                       rfi_window_stats* __restrict__ stats)
 {
     __shared__ MomSmem sm;
     const MomItem it = items[blockIdx.x];
-    const StreamView d = resolve(a.streams[it.stream], a);
+    StreamView d = resolve(a.streams[it.stream], a);
+    if (abs_add) d.abs_base += abs_add[it.stream];
     if (d.mode == RFI_MODE_CLIP) mom_apply_item<RFI_MODE_CLIP>(a, it, d, dm, stream_woff, stats, sm);
     else if (d.mode == RFI_MODE_ZERO) mom_apply_item<RFI_MODE_ZERO>(a, it, d, dm, stream_woff, stats, sm);
     else mom_apply_item<RFI_MODE_NOISE>(a, it, d, dm, stream_woff, stats, sm);
@@ -1810,21 +1853,41 @@ hipError_t launch_mom_counts(const MomStream* streams, int n_streams, int64_t ma
 }
 
 hipError_t launch_mom_select(const MomStream* streams, int n_streams, int64_t total, int32_t K,
-                             const uint8_t* mad, const uint32_t* hcnt, int32_t* dm, hipStream_t s)
+                             const uint8_t* mad, const uint32_t* hcnt, const int32_t* hist_len, int32_t* dm,
+                             hipStream_t s)
 {
     if (total <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_mom_select, dim3((unsigned)((total + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                       streams, n_streams, total, K, mad, hcnt, dm);
+                       streams, n_streams, total, K, mad, hcnt, hist_len, dm);
+    return hipGetLastError();
+}
+
+hipError_t launch_mom_extend(const MomStream* streams, int n_streams, int64_t total_ext, const uint8_t* mad,
+                             const uint8_t* hist, uint8_t* emad, hipStream_t s)
+{
+    if (total_ext <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mom_extend, dim3((unsigned)((total_ext + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       streams, n_streams, total_ext, mad, hist, emad);
+    return hipGetLastError();
+}
+
+hipError_t launch_mom_history(const MomStream* streams, int n_streams, const uint8_t* emad, uint8_t* hist,
+                              int32_t* hist_len, hipStream_t s)
+{
+    if (n_streams <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mom_history, dim3((unsigned)n_streams), dim3(kBlock), 0, s, streams, emad, hist,
+                       hist_len);
     return hipGetLastError();
 }
 
 hipError_t launch_mom_apply(const LaunchArgs& a, const MomItem* items, int64_t n_items, const int32_t* dm,
-                            const int64_t* stream_woff, rfi_window_stats* stats, hipStream_t s)
+                            const int64_t* stream_woff, const int64_t* abs_add, rfi_window_stats* stats,
+                            hipStream_t s)
 {
     if (n_items <= 0) return hipSuccess;
     if (n_items > (1 << 30)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_mom_apply, dim3((unsigned)n_items), dim3(kBlock), 0, s, a, items, dm, stream_woff,
-                       stats);
+                       abs_add, stats);
     return hipGetLastError();
 }
 

@@ -29,6 +29,7 @@ int64_t align64(int64_t n) { return (n + 63) / 64 * 64; }
 struct MomKey {
     int device;
     uintptr_t stream;  // temporaries are per stream: calls on one stream are ordered
+    int64_t pre;       // history slots per stream (0, or K - 1 with a carried history)
     uint64_t seed;
     std::vector<int64_t> L;
     std::vector<int32_t> W;
@@ -38,6 +39,7 @@ struct MomKey {
     {
         if (device != o.device) return device < o.device;
         if (stream != o.stream) return stream < o.stream;
+        if (pre != o.pre) return pre < o.pre;
         if (seed != o.seed) return seed < o.seed;
         if (L != o.L) return L < o.L;
         if (W != o.W) return W < o.W;
@@ -53,10 +55,12 @@ struct MomPlan {
     MomItem* d_items = nullptr;
     int64_t* d_woff = nullptr;
     uint8_t* d_mad = nullptr;
+    uint8_t* d_emad = nullptr;  // history slots + MADs (pre > 0)
     int32_t* d_dm = nullptr;
     uint32_t* d_hcnt = nullptr;
     rfi_window_stats* d_stats = nullptr;  // used when the caller passes none
     int32_t n_streams = 0;
+    int64_t pre = 0, total_ext = 0;
     int64_t n_items = 0, total_windows = 0, max_blocks = 0;
     uint64_t seed = 0;
 };
@@ -71,6 +75,7 @@ void mom_free(MomPlan* p)
     (void)hipFree(p->d_items);
     (void)hipFree(p->d_woff);
     (void)hipFree(p->d_mad);
+    (void)hipFree(p->d_emad);
     (void)hipFree(p->d_dm);
     (void)hipFree(p->d_hcnt);
     (void)hipFree(p->d_stats);
@@ -97,11 +102,12 @@ int alloc(T** dst, int64_t n)
 }
 
 int mom_build(int32_t n, const int64_t* L, const int32_t* W, const float* K, const int32_t* M,
-              uint64_t seed, MomPlan** out)
+              uint64_t seed, int64_t pre, MomPlan** out)
 {
     MomPlan* p = new MomPlan;
     p->n_streams = n;
     p->seed = seed;
+    p->pre = pre;
     std::vector<int32_t> mstats(n, kModeStats);
     int rc = plan_build(1, n, L, W, K, mstats.data(), seed, &p->stats_plan);
     if (rc == RFI_OK) rc = rfi_plan_set_schedule(p->stats_plan, RFI_SCHED_SPLIT);
@@ -109,7 +115,7 @@ int mom_build(int32_t n, const int64_t* L, const int32_t* W, const float* K, con
     std::vector<MomStream> ms(n);
     std::vector<MomItem> items;
     std::vector<int64_t> woff(n);
-    int64_t soff = 0, wo = 0, rows = 0;
+    int64_t soff = 0, wo = 0, eo = 0, rows = 0;
     for (int s = 0; s < n && rc == RFI_OK; ++s) {
         StreamDesc& d = desc[s];
         std::memset(&d, 0, sizeof(d));
@@ -122,11 +128,15 @@ int mom_build(int32_t n, const int64_t* L, const int32_t* W, const float* K, con
         d.mode = M[s];
         d.key = (uint32_t)s;
         const int64_t nw = (L[s] + W[s] - 1) / W[s];
+        const int64_t ne = pre + nw;  // the stream's MAD sequence: history slots, then windows
         ms[s].woff = wo;
         ms[s].nw = nw;
+        ms[s].eoff = pre > 0 ? eo : wo;
+        ms[s].pre = pre;
         ms[s].hoff = rows;
-        p->max_blocks = std::max<int64_t>(p->max_blocks, (nw + kMomBlock - 1) / kMomBlock);
-        rows += nw / kMomBlock + 1 + (nw % kMomBlock ? 1 : 0);
+        p->max_blocks = std::max<int64_t>(p->max_blocks, (ne + kMomBlock - 1) / kMomBlock);
+        rows += ne / kMomBlock + 1 + (ne % kMomBlock ? 1 : 0);
+        eo += ne;
         woff[s] = wo;
         const int64_t per = std::max<int64_t>(1, std::min<int64_t>(256, 16384 / W[s]));
         for (int64_t w = 0; w < nw; w += per)
@@ -135,12 +145,14 @@ int mom_build(int32_t n, const int64_t* L, const int32_t* W, const float* K, con
         wo += nw;
     }
     p->total_windows = wo;
+    p->total_ext = pre > 0 ? eo : 0;
     p->n_items = (int64_t)items.size();
     if (rc == RFI_OK) rc = upload(&p->d_desc, desc);
     if (rc == RFI_OK) rc = upload(&p->d_streams, ms);
     if (rc == RFI_OK) rc = upload(&p->d_items, items);
     if (rc == RFI_OK) rc = upload(&p->d_woff, woff);
     if (rc == RFI_OK) rc = alloc(&p->d_mad, wo);
+    if (rc == RFI_OK) rc = alloc(&p->d_emad, p->total_ext);
     if (rc == RFI_OK) rc = alloc(&p->d_dm, wo);
     if (rc == RFI_OK) rc = alloc(&p->d_hcnt, rows * 256);
     if (rc != RFI_OK) {
@@ -151,7 +163,8 @@ int mom_build(int32_t n, const int64_t* L, const int32_t* W, const float* K, con
     return RFI_OK;
 }
 
-int mom_execute(MomPlan* p, const void* x, void* y, rfi_window_stats* st, int32_t mom_k, hipStream_t s)
+int mom_execute(MomPlan* p, const void* x, void* y, rfi_window_stats* st, int32_t mom_k, const int64_t* abs_add,
+                uint8_t* hist, int32_t* hist_len, hipStream_t s)
 {
     if (!st) {
         if (!p->d_stats) {
@@ -163,11 +176,17 @@ int mom_execute(MomPlan* p, const void* x, void* y, rfi_window_stats* st, int32_
     int rc = plan_execute(p->stats_plan, x, y, st, s, RFI_SCHED_SPLIT);
     if (rc != RFI_OK) return rc;
     hipError_t e = launch_mom_gather(st, p->total_windows, p->d_mad, s);
+    const uint8_t* emad = p->d_mad;
+    if (e == hipSuccess && p->pre > 0) {
+        e = launch_mom_extend(p->d_streams, p->n_streams, p->total_ext, p->d_mad, hist, p->d_emad, s);
+        emad = p->d_emad;
+    }
     if (e == hipSuccess)
-        e = launch_mom_counts(p->d_streams, p->n_streams, p->max_blocks, p->d_mad, p->d_hcnt, s);
+        e = launch_mom_counts(p->d_streams, p->n_streams, p->max_blocks, emad, p->d_hcnt, s);
     if (e == hipSuccess)
-        e = launch_mom_select(p->d_streams, p->n_streams, p->total_windows, mom_k, p->d_mad, p->d_hcnt,
-                              p->d_dm, s);
+        e = launch_mom_select(p->d_streams, p->n_streams, p->total_windows, mom_k, emad, p->d_hcnt,
+                              p->pre > 0 ? hist_len : nullptr, p->d_dm, s);
+    if (e == hipSuccess && p->pre > 0) e = launch_mom_history(p->d_streams, p->n_streams, emad, hist, hist_len, s);
     if (e == hipSuccess) {
         LaunchArgs a;
         std::memset(&a, 0, sizeof(a));
@@ -176,7 +195,7 @@ int mom_execute(MomPlan* p, const void* x, void* y, rfi_window_stats* st, int32_
         a.seed = p->seed;
         a.x_base = (uint64_t)(uintptr_t)x;
         a.y_base = (uint64_t)(uintptr_t)y;
-        e = launch_mom_apply(a, p->d_items, p->n_items, p->d_dm, p->d_woff, st, s);
+        e = launch_mom_apply(a, p->d_items, p->n_items, p->d_dm, p->d_woff, abs_add, st, s);
     }
     return e == hipSuccess ? RFI_OK : hip_fail(e);
 }
@@ -186,23 +205,25 @@ std::map<MomKey, MomPlan*> g_mom;
 std::vector<MomKey> g_mom_order;
 constexpr size_t kMomCacheMax = 8;
 
-}  // namespace
-
-extern "C" {
-
-int rfi_mom_filter(const int8_t* x, int8_t* y, int32_t n_streams, const int64_t* lengths,
-                   const int32_t* windows, const float* k, const int32_t* mode, int32_t mom_k,
-                   uint64_t seed, rfi_window_stats* stats_out, void* stream)
+int mom_call(const int8_t* x, int8_t* y, int32_t n_streams, const int64_t* lengths, const int32_t* windows,
+             const float* k, const int32_t* mode, int32_t mom_k, uint64_t seed, const int64_t* abs_base,
+             uint8_t* hist, int32_t* hist_len, bool carry, rfi_window_stats* stats_out, void* stream)
 {
     if (mom_k < 1) return RFI_ERR_INVALID;
     int rc = rfi_validate(1, x, y, n_streams, lengths, windows, k, mode, stats_out);
     if (rc != RFI_OK) return rc;
+    if (carry && mom_k > 1 && n_streams > 0) {
+        if (!hist || !hist_len) return RFI_ERR_INVALID;
+        if ((uintptr_t)hist_len & 3u) return RFI_ERR_ALIGN;
+    }
+    if (abs_base && ((uintptr_t)abs_base & 7u)) return RFI_ERR_ALIGN;
     int64_t total = 0;
     rfi_layout(n_streams, lengths, windows, nullptr, nullptr, &total);
     if (n_streams == 0 || total == 0) return RFI_OK;
     MomKey key;
     if (hipGetDevice(&key.device) != hipSuccess) key.device = 0;
     key.stream = (uintptr_t)stream;
+    key.pre = carry ? (int64_t)mom_k - 1 : 0;
     key.seed = seed;
     key.L.assign(lengths, lengths + n_streams);
     key.W.assign(windows, windows + n_streams);
@@ -221,12 +242,33 @@ int rfi_mom_filter(const int8_t* x, int8_t* y, int32_t n_streams, const int64_t*
             g_mom.erase(old);
             g_mom_order.erase(g_mom_order.begin());
         }
-        rc = mom_build(n_streams, lengths, windows, k, mode, seed, &p);
+        rc = mom_build(n_streams, lengths, windows, k, mode, seed, key.pre, &p);
         if (rc != RFI_OK) return rc;
         g_mom[key] = p;
         g_mom_order.push_back(key);
     }
-    return mom_execute(p, x, y, stats_out, mom_k, (hipStream_t)stream);
+    return mom_execute(p, x, y, stats_out, mom_k, abs_base, hist, hist_len, (hipStream_t)stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+int rfi_mom_filter(const int8_t* x, int8_t* y, int32_t n_streams, const int64_t* lengths,
+                   const int32_t* windows, const float* k, const int32_t* mode, int32_t mom_k,
+                   uint64_t seed, rfi_window_stats* stats_out, void* stream)
+{
+    return mom_call(x, y, n_streams, lengths, windows, k, mode, mom_k, seed, nullptr, nullptr, nullptr, false,
+                    stats_out, stream);
+}
+
+int rfi_mom_filter_carry(const int8_t* x, int8_t* y, int32_t n_streams, const int64_t* lengths,
+                         const int32_t* windows, const float* k, const int32_t* mode, int32_t mom_k,
+                         uint64_t seed, const int64_t* abs_base, uint8_t* mad_history, int32_t* history_len,
+                         rfi_window_stats* stats_out, void* stream)
+{
+    return mom_call(x, y, n_streams, lengths, windows, k, mode, mom_k, seed, abs_base, mad_history, history_len,
+                    mom_k > 1, stats_out, stream);
 }
 
 }  // extern "C"

@@ -141,3 +141,65 @@ def test_two_streams_same_signature(gpu):
     torch.cuda.synchronize()
     _check(xa, L, W, K, M, 64, 4, ya.cpu().numpy(), rfi.stats_numpy(sta), padding=False)
     _check(xb, L, W, K, M, 64, 4, yb.cpu().numpy(), rfi.stats_numpy(stb), padding=False)
+
+
+def _pack_np(parts):
+    offs, total = synth.packed_offsets([len(p) for p in parts])
+    out = np.zeros(max(total, 64), dtype=np.int8)
+    for o, p in zip(offs, parts):
+        out[o:o + len(p)] = p
+    return out[:max(total, 1)], offs
+
+
+@pytest.mark.parametrize("mom_k", [1, 7, 64, 300])
+def test_carry_chained_equals_whole_stream(gpu, mom_k):
+    # three streams cut at window boundaries into four calls each (the last
+    # piece of each stream ends with a short window): the chained calls give
+    # the bytes and statistics of one call over the whole streams
+    Ws, Ks, Ms = [4096, 512, 1000], [3.0, 2.5, 3.5], [2, 1, 0]
+    nwin = [[30, 1, 45, 20], [200, 7, 0, 90], [60, 60, 3, 40]]
+    tails = [100, 17, 999]
+    specs = [synth.StreamSpec(sum(nw) * W + t, W, k, m, 6.0 + 4 * i, 0.01, 8, 3000)
+             for i, (nw, W, k, m, t) in enumerate(zip(nwin, Ws, Ks, Ms, tails))]
+    xw, L, W, K, M = _batch(specs, 777 + mom_k)
+    so = rfi.layout(L, W)[0]
+    streams = [xw[so[s]:so[s] + L[s]] for s in range(3)]
+    y_ref, st_ref = _run(xw, L, W, K, M, mom_k, 21, gpu)
+    ns = 3
+    hist = torch.zeros((ns, max(mom_k - 1, 1)), dtype=torch.uint8, device=gpu)
+    hlen = torch.zeros(ns, dtype=torch.int32, device=gpu)
+    pos = [0, 0, 0]
+    outs = [[] for _ in range(ns)]
+    stats = [[] for _ in range(ns)]
+    for c in range(4):
+        lens = [nwin[s][c] * W[s] + (tails[s] if c == 3 else 0) for s in range(ns)]
+        parts = [streams[s][pos[s]:pos[s] + lens[s]] for s in range(ns)]
+        xb, offs = _pack_np(parts)
+        xd = torch.from_numpy(xb.copy()).to(gpu)
+        absb = torch.tensor(pos, dtype=torch.int64, device=gpu)
+        y, st = rfi.mom_filter_carry(xd, lens, W, K, M, mom_k, absb, hist if mom_k > 1 else None,
+                                     hlen if mom_k > 1 else None, seed=21)
+        torch.cuda.synchronize()
+        yn = y.cpu().numpy()
+        stn = rfi.stats_numpy(st) if st is not None else np.zeros(0, dtype=rfi.STATS_DTYPE)
+        wo = rfi.layout(lens, W)[1]
+        for s in range(ns):
+            outs[s].append(yn[offs[s]:offs[s] + lens[s]])
+            nws = (lens[s] + W[s] - 1) // W[s]
+            stats[s].append(stn[wo[s]:wo[s] + nws])
+            pos[s] += lens[s]
+        if mom_k > 1:
+            assert hlen.cpu().numpy().tolist() == [min(mom_k - 1, sum((nwin[s][j] + (1 if (j == 3 and tails[s]) else 0))
+                                                                       for j in range(c + 1))) for s in range(ns)]
+    wo_ref = rfi.layout(L, W)[1]
+    for s in range(ns):
+        got = np.concatenate(outs[s])
+        assert np.array_equal(got, y_ref[so[s]:so[s] + L[s]]), (mom_k, s)
+        nws = (L[s] + W[s] - 1) // W[s]
+        assert np.array_equal(np.concatenate(stats[s]), st_ref[wo_ref[s]:wo_ref[s] + nws]), (mom_k, s)
+
+
+def test_carry_errors(gpu):
+    x = torch.zeros(4096, dtype=torch.int8, device=gpu)
+    with pytest.raises(rfi.RfiError):
+        rfi.mom_filter_carry(x, [4096], [512], [3.0], [0], 4, None, None, None)
