@@ -555,6 +555,31 @@ def bench_mom(args, dev, x, y, L):
         ms = _time_events(fn, max(10, args.steps // 5), stream)
         res[name] = {"ms": round(ms, 4), "gsamples_s": round(n / ms / 1e6, 1),
                      "gb_s": round(ab / ms / 1e6, 1), "roofline_frac": round(ab / ms / 1e6 / HBM_PEAK_GBS, 4)}
+    # Real-time use: one 2^20-sample block of every stream per call, the MAD
+    # history (4095 windows) and the sample base carried on the device.
+    blk = 1 << 20
+    xb = x[:ns * blk].view(ns, blk).contiguous().view(-1)
+    yb = torch.empty_like(xb)
+    hist = torch.zeros((ns, 4095), dtype=torch.uint8, device=dev)
+    hlen = torch.zeros(ns, dtype=torch.int32, device=dev)
+    absb = torch.zeros(ns, dtype=torch.int64, device=dev)
+    stb = torch.empty((ns * blk // 4096, 4), dtype=torch.int32, device=dev)
+    Lb = np.full(ns, blk, dtype=np.int64)
+    Mb = np.full(ns, 2, dtype=np.int32)
+
+    def call():
+        _lib._check(_lib.load().rfi_mom_filter_carry(
+            _lib._tptr(xb), _lib._tptr(yb), ns, _lib._ptr(Lb), _lib._ptr(Ws), _lib._ptr(Ks), _lib._ptr(Mb), 4096, 1,
+            _lib._tptr(absb), _lib._tptr(hist), _lib._tptr(hlen), _lib._tptr(stb), _lib._stream_handle(stream)),
+            "rfi_mom_filter_carry")
+        absb.add_(blk)
+    for _ in range(3):
+        call()
+    ms = _time_events(call, max(10, args.steps // 5), stream)
+    res["carried_blocks_noise"] = {"workload": "60 streams, one 2^20-sample block each per call, history of 4095 MADs "
+                                               "carried on the device, noise",
+                                   "ms_per_call": round(ms, 4), "deadline_ms": round(DEADLINE_NS / 1e6, 5),
+                                   "gsamples_s": round(ns * blk / ms / 1e6, 1)}
     return res
 
 
