@@ -1,6 +1,8 @@
 """Host-only checks of the C ABI (no GPU): the library loads, exports every
 function its header declares, and its pure-host calls behave."""
 import ctypes
+import glob
+import os
 import math
 
 import numpy as np
@@ -86,3 +88,29 @@ def test_no_cpu_fallback():
     rc = lib.rfi_plan_create(1, 1, L.ctypes.data, W.ctypes.data, K.ctypes.data, M.ctypes.data, 0,
                              ctypes.byref(h))
     assert rc != 0
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # one GPU only: --gpus above 1 exits with a message, before touching a device
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr
+
+
+def test_profile_summaries_parse():
+    # every committed profile summary names its command and, for the traffic
+    # summary, the calibration and the kernel-source hash bench.py checks
+    from paper_1710_08576_amd import profiling
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    mds = sorted(glob.glob(os.path.join(root, "profiles", "*.md")))
+    assert mds
+    for fn in mds:
+        text = open(fn).read()
+        assert "rocprofv3" in text, fn
+    summ = profiling.load_summary(os.path.join(root, "profiles", "i8_w4096_plain_scale.md"))
+    assert summ["calibration"]["copy_bytes"] > 0
+    assert len(summ["kernel_source_sha256"]) == 64
