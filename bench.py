@@ -91,8 +91,8 @@ def main():
                          "(a kernel of known traffic, to calibrate hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(streams shard across GPUs with no exchange; see DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU: there is no multi-GPU path (streams would shard "
+              "across GPUs with no exchange)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

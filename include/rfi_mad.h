@@ -63,7 +63,7 @@ typedef enum {
     RFI_OK = 0,
     RFI_ERR_INVALID = -1,     /* bad argument value or size                  */
     RFI_ERR_ALIGN = -2,       /* x, y or stats not 16-byte aligned           */
-    RFI_ERR_UNSUPPORTED = -3, /* valid request this build cannot serve       */
+    RFI_ERR_UNSUPPORTED = -3, /* valid request the library cannot serve     */
     RFI_ERR_NOMEM = -4,       /* device or host allocation failed            */
     RFI_ERR_HIP = -5,         /* a HIP runtime call failed (see status text) */
     RFI_ERR_BUSY = -6         /* serving: admission refused (budget/slots)   */
