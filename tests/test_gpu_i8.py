@@ -207,3 +207,32 @@ def test_graph_replays_each_checked(gpu, elem, sched):
     check_against_oracle(xd.cpu(), specs, 3, yd.cpu().numpy(), rfi.stats_numpy(st), check_padding=False)
     g.close()
     e.close()
+
+
+def test_autotune_picks_a_schedule_and_keeps_the_bytes(gpu):
+    """The autotuner times every schedule on the plan's buffers and keeps the
+    fastest: the result is a valid schedule, the plan then runs it (with and
+    without a graph) and every run equals the oracle; a second plan of the
+    same signature left on auto picks the tuned schedule up."""
+    specs = synth.batching(n_streams=16, lo=1 << 15, hi=1 << 18, seed=8)
+    x = synth.gen_packed(specs, seed=8, tag=8)
+    L, W, K, M = unpack(specs)
+    xd = x.to(gpu)
+    p = rfi.Plan(1, L, W, K, M, seed=5)
+    yd = torch.empty_like(xd)
+    st = torch.empty((p.n_windows, 4), dtype=torch.int32, device=gpu)
+    best, ms = p.autotune(xd, yd, st, iters=3)
+    torch.cuda.synchronize()
+    assert best in set(rfi.SCHEDULES.values()) - {0} and ms > 0
+    check_against_oracle(x, specs, 5, yd.cpu().numpy(), rfi.stats_numpy(st), check_padding=False)
+    for graph in (False, True):
+        yd.fill_(0)
+        st.fill_(-1)
+        p.set_graph(graph)
+        p.execute(xd, yd, st)
+        torch.cuda.synchronize()
+        check_against_oracle(x, specs, 5, yd.cpu().numpy(), rfi.stats_numpy(st), check_padding=False)
+    q = rfi.Plan(1, L, W, K, M, seed=5)
+    assert q.schedule() == best
+    p.close()
+    q.close()
