@@ -331,7 +331,7 @@ int plan_build(int elem, int32_t n, const int64_t* L, const int32_t* W, const fl
         d.mode = M[s];
         d.key = (uint32_t)s;
         d.head_len = 0;
-        d.flags = 0;
+        d.flags = kPadded;
         const int64_t nw = (L[s] + W[s] - 1) / W[s];
         const int cls = tile_class(elem, W[s]);
         int64_t first_generic = 0;

@@ -29,9 +29,12 @@ struct StreamDesc {
     int32_t mode;        // rfi_mode
     uint32_t key;        // Philox key word 1 (stream index or stream id)
     int32_t head_len;    // carry samples at head_off
-    int32_t flags;       // kNoStats
+    int32_t flags;       // kNoStats, kPadded
 };
 constexpr int32_t kNoStats = 1;
+// The stream lies in the packed batch layout, whose buffers extend to a
+// multiple of 64 elements past its end (reads may round up to 16 bytes).
+constexpr int32_t kPadded = 2;
 
 // A stream as the kernels see it, with addresses resolved.
 struct StreamView {
@@ -46,6 +49,7 @@ struct StreamView {
     int32_t mode;
     uint32_t key;
     int32_t head_len;
+    int32_t padded;  // kPadded
 };
 
 // One unit of work for a workgroup.
@@ -115,6 +119,7 @@ __host__ __device__ inline StreamView resolve(const StreamDesc& d, const LaunchA
     v.mode = d.mode;
     v.key = d.key;
     v.head_len = d.head_len;
+    v.padded = (d.flags & kPadded) != 0;
     return v;
 }
 

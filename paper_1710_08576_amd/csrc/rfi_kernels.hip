@@ -12,16 +12,22 @@
 //   d with C[m+d] - C[m-d-1] >= r + 1, i.e. the |x - m| histogram folded out
 //   of the same counts, so the samples are histogrammed once.  The flag
 //   count is N - (C[hi] - C[lo-1]) and needs no extra pass.
-// int16 windows: two-digit (8+8 bit) radix select, once for the median on
-//   x + 32768 and once for the MAD on |x - m|.
+// int16 windows (W 8192 tiles): a 12-bit coarse histogram of x + 32768 and
+//   a 4-bit fine digit give the median; the MAD is bracketed to 16 values
+//   from the same cumulative coarse counts and resolved by one filtered pass
+//   over |x - m|.  Other int16 windows: an 8+8-bit radix select over global
+//   memory (generic path).
 // Replacement: the per-sample test |x - m| > t equals x < m - floor(t) or
 //   x > m + floor(t) because |x - m| is an integer, so after one binary32
 //   threshold per window everything is integer; int8 samples are clamped
 //   four to a dword with packed 16-bit max/min.
-// Noise: flagged dwords of a wave are compacted into a list, every lane
-//   draws one Philox4x64-10 block per list entry, and the owners merge the
-//   noise bytes back, so the cost follows the number of flagged dwords, not
-//   the worst lane.
+// Noise: the flagged 4-sample parts of a workgroup's tile are pooled into
+//   one list, one thread draws one Philox4x64-10 block per entry, and the
+//   owners merge the noise bytes back, so the cost follows the number of
+//   flagged parts, not the worst lane.
+// Also here: the several-outputs tile kernel, the median-of-MAD passes
+//   (MAD gather, block counts, search, history, replacement) and the serving
+//   carry copy.
 #include "rfi_device.hpp"
 #include "rfi_internal.hpp"
 
@@ -673,7 +679,12 @@ __device__ __forceinline__ TileStats i8_tile_any(const StreamView& d, int64_t fi
 // One workgroup per window; two passes over the samples in global memory.
 // ---------------------------------------------------------------------------
 struct GenericSmem {
-    uint32_t hist[4 * 256];  // int16 radix uses four digit histograms
+    union {
+        uint32_t hist[4 * 256];                            // int16 radix: four digit histograms
+        __align__(16) uint32_t whist[4 * kWaveHistWords];  // int8 register path: per-wave replicas
+    };
+    __align__(16) uint32_t tot[256];
+    __align__(16) uint32_t pc[kPadC];
     WinParams prm;
     int32_t sel[4];
     uint32_t flagged;
@@ -686,7 +697,7 @@ __device__ __forceinline__ int load_logical(const StreamView& d, int64_t i)
                           : (int)gload(static_cast<const T*>(d.x) + (i - d.head_len));
 }
 
-// Noise sample for absolute index j (one Philox block per 16 samples).
+// Noise sample for absolute index j (one Philox block per 4 samples).
 __device__ __forceinline__ int noise_sample(int64_t j, uint64_t seed, uint32_t key, int m, int sq8,
                                             int vmin, int vmax)
 {
@@ -697,11 +708,128 @@ __device__ __forceinline__ int noise_sample(int64_t j, uint64_t seed, uint32_t k
     return (int)min(max((int64_t)m + q, (int64_t)vmin), (int64_t)vmax);
 }
 
+// Register path for a generic int8 window in zero or clip mode (or
+// statistics only) with no head segment, 16-byte aligned input and output,
+// and 512 <= n samples in at most 1024 16-byte chunks (noise windows take
+// the plain path, which keeps the draws out of this path's registers): the
+// aligned chunks covering [a, a + n) are loaded (four per lane),
+// their in-window bytes counted into per-wave replicated histograms, the
+// counts summed and selected as the wide tiles do, and the chunks replaced
+// in registers and stored (whole chunks as one 16-byte store, the two edge
+// chunks byte by byte, so a neighbouring window's bytes are never written).
+constexpr int kGenericRegMin = 512;
+
+__device__ __forceinline__ bool i8_generic_reg_ok(const StreamView& d, int64_t a, int n)
+{
+    if (d.head_len != 0 || d.mode == RFI_MODE_NOISE || n < kGenericRegMin) return false;
+    if (((uintptr_t)d.x | (uintptr_t)d.y) & 15u) return false;
+    // the last chunk may reach up to 15 bytes past the window: inside the
+    // stream, or inside the packed layout's padding
+    if (!d.padded && ((a + n + 15) & ~(int64_t)15) > d.length) return false;
+    return ((a + n + 15) >> 4) - (a >> 4) <= 4 * kBlock;
+}
+
+__device__ __forceinline__ uint32_t byte_of(uint32_t v, int b) { return (v >> (8 * b)) & 0xFFu; }
+
+__device__ void i8_generic_reg(const StreamView& d, int64_t w, int64_t a, int n, GenericSmem& sm)
+{
+    const int tid = (int)threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    const uint8_t* xb = static_cast<const uint8_t*>(d.x);
+    uint8_t* yb = static_cast<uint8_t*>(d.y);
+    const int64_t c0 = a >> 4, e = a + n;
+    const int64_t nch = ((e + 15) >> 4) - c0;
+    uint32_t v[16];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t c = tid + k * kBlock;
+        uint4 t = make_uint4(0, 0, 0, 0);
+        if (c < nch) t = gload16_nt(xb + (c0 + c) * 16);
+        v[4 * k] = t.x;
+        v[4 * k + 1] = t.y;
+        v[4 * k + 2] = t.z;
+        v[4 * k + 3] = t.w;
+    }
+    __syncthreads();  // the previous item is done with the scratch
+    uint32_t* h = sm.whist + wave * kWaveHistWords;
+    wide_hist_zero(h);
+    sm.tot[tid] = 0;
+    __syncthreads();
+    uint32_t* hl = h + (lane & 3) * kRepStride;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t c = tid + k * kBlock;
+        if (c >= nch) continue;
+        const int64_t cb = (c0 + c) * 16;
+        if (cb >= a && cb + 16 <= e) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) wide_hist_add(hl, v[4 * k + j]);
+        } else {
+#pragma unroll
+            for (int b = 0; b < 16; ++b)
+                if (cb + b >= a && cb + b < e) atomicAdd(hl + byte_of(v[4 * k + b / 4], b % 4), 1u);
+        }
+    }
+    wave_sync();
+    uint32_t cnt[4];
+    wide_hist_totals(h, cnt);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) atomicAdd(&sm.tot[lane * 4 + j], cnt[j]);
+    __syncthreads();
+    if (wave == 0) {
+        const uint4 t = *reinterpret_cast<const uint4*>(sm.tot + lane * 4);
+        cnt[0] = t.x;
+        cnt[1] = t.y;
+        cnt[2] = t.z;
+        cnt[3] = t.w;
+        int mb, D;
+        wide_select(cnt, sm.pc, (uint32_t)((n - 1) / 2 + 1), mb, D);
+        WinParams p;
+        rfi_window_stats s;
+        wide_params(sm.pc, mb, D, d.k, n, p, s);
+        if (lane == 0) {
+            sm.prm = p;
+            if (d.stats) d.stats[w] = s;
+        }
+    }
+    __syncthreads();
+    if (d.mode == kModeStats) return;
+    const WinParams p = sm.prm;
+    const uint32_t lo = rep_i16(p.lo * 256), hi = rep_i16(p.hi * 256);
+    const uint32_t lo_u = rep_i16((p.lo + 128) * 256), hi_u = rep_i16((p.hi + 128) * 256);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t c = tid + k * kBlock;
+        if (c >= nch) continue;
+        const int64_t cb = (c0 + c) * 16;
+        uint32_t r[4];
+        const bool clip = d.mode == RFI_MODE_CLIP;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t x = v[4 * k + j];
+            r[j] = clip ? clamp_i8x4(x, lo, hi) : byte_perm(0u, x, flag_sel_i8x4(x, lo_u, hi_u));
+        }
+        if (cb >= a && cb + 16 <= e) {
+            gstore16_nt(yb + cb, make_uint4(r[0], r[1], r[2], r[3]));
+        } else {
+#pragma unroll
+            for (int b = 0; b < 16; ++b)
+                if (cb + b >= a && cb + b < e) gstore(yb + cb + b, (uint8_t)byte_of(r[b / 4], b % 4));
+        }
+    }
+}
+
+// REG: the register path is compiled in (kernels that may see zero or clip
+// windows).
+template <bool REG = true>
 __device__ void i8_generic(const StreamView& d, int64_t w, uint64_t seed, GenericSmem& sm)
 {
     const int W = d.window;
     const int64_t a = w * (int64_t)W;
     const int n = (int)min((int64_t)W, d.length - a);
+    if (REG && i8_generic_reg_ok(d, a, n)) {
+        i8_generic_reg(d, w, a, n, sm);
+        return;
+    }
     const int tid = (int)threadIdx.x;
     int8_t* y = static_cast<int8_t*>(d.y);
     __syncthreads();
@@ -1270,7 +1398,7 @@ __global__ __launch_bounds__(kBlock) void k_i8_fused(LaunchArgs a)
         const Item item = a.items[it];
         const StreamView d = resolve(a.streams[item.stream], a);
         if (item.kind == kItemGeneric) {
-            i8_generic(d, item.first, a.seed, sm.g);
+            i8_generic<(MODES & 3) != 0>(d, item.first, a.seed, sm.g);
             return;
         }
         // Items of different classes may follow each other: keep the LDS

@@ -127,6 +127,7 @@ int mom_build(int32_t n, const int64_t* L, const int32_t* W, const float* K, con
         d.k = K[s];
         d.mode = M[s];
         d.key = (uint32_t)s;
+        d.flags = kPadded;
         const int64_t nw = (L[s] + W[s] - 1) / W[s];
         const int64_t ne = pre + nw;  // the stream's MAD sequence: history slots, then windows
         ms[s].woff = wo;

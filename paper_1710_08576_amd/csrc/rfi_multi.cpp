@@ -85,6 +85,7 @@ int multi_build(int32_t n_out, int32_t n, const int64_t* L, const int32_t* W, co
             d.k = K[(int64_t)o * n + s];
             d.mode = M[(int64_t)o * n + s];
             d.key = (uint32_t)s;
+            d.flags = kPadded;
         }
         const int64_t nw = (L[s] + W[s] - 1) / W[s];
         const int cls = i8_tile_class(W[s]);
