@@ -236,3 +236,27 @@ def test_autotune_picks_a_schedule_and_keeps_the_bytes(gpu):
     assert q.schedule() == best
     p.close()
     q.close()
+
+
+@pytest.mark.parametrize("W", [511, 512, 513, 1023, 1537, 3000, 8191, 16000, 16369, 16383])
+def test_generic_register_path_edges(gpu, W):
+    """Generic windows around the register path's limits (512 samples, 1024
+    chunks) with window starts at every 16-byte phase, zero and clip mode,
+    streams whose ends fall in the padding and a saturated, bimodal stream:
+    equal to the oracle, no byte outside a window written (the sentinel
+    padding of the helpers)."""
+    rng = np.random.default_rng(W)
+    specs = []
+    for i, mode in enumerate((rfi.ZERO, rfi.CLIP, rfi.ZERO, rfi.CLIP)):
+        L = W * (3 + i) + int(rng.integers(1, 40))
+        specs.append(synth.StreamSpec(L, W, [2.0, 3.0, 4.0, 1.0][i], mode, 6.0 + 5 * i, 0.02, 4, 700))
+    x = synth.gen_packed(specs, seed=W, tag=9)
+    # one stream of extremes: -128/127 halves, so the median and MAD sit at the ends
+    so = rfi.layout([s.length for s in specs], [s.window for s in specs])[0]
+    L3 = specs[3].length
+    x[so[3]:so[3] + L3] = torch.where(torch.arange(L3) % 2 == 0, torch.tensor(-128, dtype=torch.int8),
+                                      torch.tensor(127, dtype=torch.int8))
+    y, st = gpu_run(x, specs, 13, gpu)
+    check_against_oracle(x, specs, 13, y, st)
+    y, st = gpu_run(x, specs, 13, gpu, schedule="fused", graph=True)
+    check_against_oracle(x, specs, 13, y, st)
