@@ -1592,18 +1592,52 @@ __global__ __launch_bounds__(256) void k_mom_counts(const MomStream* __restrict_
     const int64_t nb = (st.pre + st.nw + kMomBlock - 1) / kMomBlock;
     uint32_t run = 0;
     row[0] = 0;
-    for (int64_t b = 1; b <= nb; ++b) {
-        run += row[b * 256];
-        row[b * 256] = run;
+    // 16 rows per batch: their loads are in flight together
+    for (int64_t b0 = 1; b0 <= nb; b0 += 16) {
+        uint32_t t[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) t[i] = b0 + i <= nb ? row[(b0 + i) * 256] : 0u;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            run += t[i];
+            if (b0 + i <= nb) row[(b0 + i) * 256] = run;
+        }
     }
 }
 
-// #{j < p : mad_j <= v} from the block table and the partial block.
-__device__ __forceinline__ uint32_t mom_prefix(const uint8_t* m, const uint32_t* h, int64_t p, int v)
+// The partial block of prefix p: entries [kMomBlock * (p / kMomBlock), p)
+// of a MAD sequence, four to a dword (entry 4i + c in byte c of w[i]), the
+// bytes from p on set to 255.  Only dwords holding an entry are read.
+__device__ __forceinline__ void mom_partial(const uint8_t* m, int64_t p, uint32_t (&w)[16])
 {
-    const int64_t b = p / kMomBlock;
-    uint32_t c = h[b * 256 + v];
-    for (int64_t j = b * kMomBlock; j < p; ++j) c += m[j] <= v ? 1u : 0u;
+    const int64_t j0 = p / kMomBlock * kMomBlock;
+    const int n = (int)(p - j0);  // 0 .. kMomBlock - 1
+    const uintptr_t a = (uintptr_t)(m + j0);
+    const uint32_t* base = reinterpret_cast<const uint32_t*>(a & ~(uintptr_t)3);
+    const int off = (int)(a & 3);
+    uint32_t r[17];
+#pragma unroll
+    for (int i = 0; i < 17; ++i) r[i] = 4 * i < off + n ? base[i] : 0u;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const uint32_t x = __builtin_amdgcn_alignbyte(r[i + 1], r[i], (uint32_t)off);
+        const int valid = n - 4 * i;  // entries in this dword
+        w[i] = valid >= 4 ? x : valid <= 0 ? ~0u : x | (~0u << (8 * valid));
+    }
+}
+
+// Number of bytes <= v (v < 255) in w: each byte is subtracted from v in
+// a 16-bit lane with bit 15 preset, which stays set exactly when the byte
+// is at most v.
+__device__ __forceinline__ uint32_t count_le(const uint32_t (&w)[16], int v)
+{
+    const uint32_t V = (uint32_t)v * 0x00010001u | 0x80008000u;
+    uint32_t c = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        c += __popc((V - (w[i] & 0x00FF00FFu)) & 0x80008000u);
+        c += __popc((V - ((w[i] >> 8) & 0x00FF00FFu)) & 0x80008000u);
+    }
     return c;
 }
 
@@ -1630,11 +1664,16 @@ __global__ __launch_bounds__(kBlock) void k_mom_select(const MomStream* __restri
     const int64_t a = max(st.pre - H, p + 1 - (int64_t)K), b = p + 1;
     const uint32_t need = (uint32_t)((b - a - 1) / 2 + 1);
     const uint8_t* m = mad + st.eoff;
-    const uint32_t* h = hcnt + st.hoff * 256;
+    const uint32_t* ha = hcnt + (st.hoff + a / kMomBlock) * 256;
+    const uint32_t* hb = hcnt + (st.hoff + b / kMomBlock) * 256;
+    // #{j < p : mad_j <= v} = block table row p / kMomBlock + partial block
+    uint32_t wa[16], wb[16];
+    mom_partial(m, a, wa);
+    mom_partial(m, b, wb);
     int lo = 0, hi = 255;  // smallest v with #{a <= j < b : mad_j <= v} >= need
     while (lo < hi) {
-        const int mid = (lo + hi) / 2;
-        if (mom_prefix(m, h, b, mid) - mom_prefix(m, h, a, mid) >= need) hi = mid;
+        const int mid = (lo + hi) / 2;  // < 255
+        if ((hb[mid] + count_le(wb, mid)) - (ha[mid] + count_le(wa, mid)) >= need) hi = mid;
         else lo = mid + 1;
     }
     dm[g] = lo;

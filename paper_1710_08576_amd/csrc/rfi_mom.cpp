@@ -152,8 +152,10 @@ int mom_build(int32_t n, const int64_t* L, const int32_t* W, const float* K, con
     if (rc == RFI_OK) rc = upload(&p->d_streams, ms);
     if (rc == RFI_OK) rc = upload(&p->d_items, items);
     if (rc == RFI_OK) rc = upload(&p->d_woff, woff);
-    if (rc == RFI_OK) rc = alloc(&p->d_mad, wo);
-    if (rc == RFI_OK) rc = alloc(&p->d_emad, p->total_ext);
+    // The selection reads a stream's MAD sequence in whole aligned dwords:
+    // 4 bytes past the end keep the last one inside the allocation.
+    if (rc == RFI_OK) rc = alloc(&p->d_mad, wo + 4);
+    if (rc == RFI_OK && p->total_ext > 0) rc = alloc(&p->d_emad, p->total_ext + 4);
     if (rc == RFI_OK) rc = alloc(&p->d_dm, wo);
     if (rc == RFI_OK) rc = alloc(&p->d_hcnt, rows * 256);
     if (rc != RFI_OK) {
