@@ -63,12 +63,16 @@ struct MomPlan {
     int64_t pre = 0, total_ext = 0;
     int64_t n_items = 0, total_windows = 0, max_blocks = 0;
     uint64_t seed = 0;
+    int device = 0;  // the plan's buffers and kernels live here
 };
 
 void mom_free(MomPlan* p)
 {
     if (!p) return;
     if (p->stats_plan) plan_free(p->stats_plan);
+    int cur = 0;
+    const bool have = hipGetDevice(&cur) == hipSuccess;
+    if (have && cur != p->device) (void)hipSetDevice(p->device);
     (void)hipDeviceSynchronize();
     (void)hipFree(p->d_desc);
     (void)hipFree(p->d_streams);
@@ -79,6 +83,7 @@ void mom_free(MomPlan* p)
     (void)hipFree(p->d_dm);
     (void)hipFree(p->d_hcnt);
     (void)hipFree(p->d_stats);
+    if (have && cur != p->device) (void)hipSetDevice(cur);
     delete p;
 }
 
@@ -105,6 +110,7 @@ int mom_build(int32_t n, const int64_t* L, const int32_t* W, const float* K, con
               uint64_t seed, int64_t pre, MomPlan** out)
 {
     MomPlan* p = new MomPlan;
+    if (hipGetDevice(&p->device) != hipSuccess) p->device = 0;
     p->n_streams = n;
     p->seed = seed;
     p->pre = pre;

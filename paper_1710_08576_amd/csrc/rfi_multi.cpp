@@ -53,14 +53,19 @@ struct MultiPlan {
     Item* d_items = nullptr;
     std::vector<int64_t> cls_begin, cls_count;  // tile items per class, then generic
     int64_t gen_begin = 0, gen_count = 0;
+    int device = 0;  // the plan's buffers and kernels live here
 };
 
 void multi_free(MultiPlan* p)
 {
     if (!p) return;
+    int cur = 0;
+    const bool have = hipGetDevice(&cur) == hipSuccess;
+    if (have && cur != p->device) (void)hipSetDevice(p->device);
     (void)hipDeviceSynchronize();
     for (auto* d : p->d_desc) (void)hipFree(d);
     (void)hipFree(p->d_items);
+    if (have && cur != p->device) (void)hipSetDevice(cur);
     delete p;
 }
 
@@ -68,6 +73,7 @@ int multi_build(int32_t n_out, int32_t n, const int64_t* L, const int32_t* W, co
                 const int32_t* M, uint64_t seed, MultiPlan** out)
 {
     MultiPlan* p = new MultiPlan;
+    if (hipGetDevice(&p->device) != hipSuccess) p->device = 0;
     p->n_out = n_out;
     p->seed = seed;
     std::vector<std::vector<Item>> groups(kI8Classes + 1);

@@ -253,6 +253,7 @@ struct PowPlan {
     int64_t* d_parts = nullptr;
     int32_t n_rows = 0;
     int64_t n_parts = 0, n_blocks = 0, ppb = 1;
+    int device = 0;
 };
 
 std::mutex g_pow_mu;
@@ -263,9 +264,14 @@ constexpr size_t kPowCacheMax = 8;
 void pow_free(PowPlan* p)
 {
     if (!p) return;
+    // the plan's kernels run on its own device, which need not be current
+    int cur = 0;
+    const bool have = hipGetDevice(&cur) == hipSuccess;
+    if (have && cur != p->device) (void)hipSetDevice(p->device);
     (void)hipDeviceSynchronize();
     (void)hipFree(p->d_rows);
     (void)hipFree(p->d_parts);
+    if (have && cur != p->device) (void)hipSetDevice(cur);
     delete p;
 }
 
@@ -313,6 +319,7 @@ int pow_plan(int elem, int32_t n, const int64_t* L, int32_t block, hipStream_t s
         return RFI_ERR_INVALID;
     }
     p->n_rows = n;
+    p->device = key.device;
     hipError_t e = hipMalloc(&p->d_rows, sizeof(PowRow) * rows.size());
     if (e == hipSuccess) e = hipMemcpy(p->d_rows, rows.data(), sizeof(PowRow) * rows.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && elem > 0 && p->ppb > 1 && p->n_parts > 0)
