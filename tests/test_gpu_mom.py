@@ -43,7 +43,10 @@ def _batch(specs, seed):
         [s.mode for s in specs]
 
 
-@pytest.mark.parametrize("mom_k", [1, 2, 7, 64, 4096])
+# K around multiples of the 64-window count blocks: the search's partial
+# blocks at both ends of a range take every length, on MAD sequences that
+# start at arbitrary byte offsets (window counts 38, 150, 62, ...)
+@pytest.mark.parametrize("mom_k", [1, 2, 7, 63, 64, 65, 129, 4096])
 def test_mixed_batch(gpu, mom_k):
     specs = []
     for i, (W, L) in enumerate([(4096, 4096 * 37 + 100), (512, 512 * 150), (1000, 61_111),
@@ -151,7 +154,7 @@ def _pack_np(parts):
     return out[:max(total, 1)], offs
 
 
-@pytest.mark.parametrize("mom_k", [1, 7, 64, 300])
+@pytest.mark.parametrize("mom_k", [1, 7, 64, 65, 129, 300])
 def test_carry_chained_equals_whole_stream(gpu, mom_k):
     # three streams cut at window boundaries into four calls each (the last
     # piece of each stream ends with a short window): the chained calls give
