@@ -206,3 +206,58 @@ def test_carry_errors(gpu):
     x = torch.zeros(4096, dtype=torch.int8, device=gpu)
     with pytest.raises(rfi.RfiError):
         rfi.mom_filter_carry(x, [4096], [512], [3.0], [0], 4, None, None, None)
+
+
+def _oracle_stream(xs, s, W, k, m, mom_k, seed):
+    # stream s alone, behind s empty streams, so that its noise key is s
+    yo, sto = oracle.mom_filter_batch(xs, [0] * s + [len(xs)], [W] * (s + 1), [k] * (s + 1), [m] * (s + 1),
+                                      mom_k, seed=seed)
+    return yo[:len(xs)], sto
+
+
+def test_large_mixed_batch_matches_oracle(gpu):
+    # 72 M samples in six streams of mixed W, k and mode (noise in four):
+    # every stream's bytes and statistics equal the oracle's
+    Ws = [4096, 1000, 8192, 4096, 2048, 777]
+    Ks = [3.0, 2.5, 3.5, 3.0, 4.0, 3.0]
+    Ms = [2, 2, 0, 2, 1, 2]
+    specs = [synth.StreamSpec(12_000_000 + 777 * i, Ws[i], Ks[i], Ms[i], 6.0 + 3 * i, 0.01, 8, 3000)
+             for i in range(6)]
+    L = [sp.length for sp in specs]
+    xd = synth.gen_packed(specs, 5, 41, device=gpu)
+    y, st = rfi.mom_filter(xd, L, Ws, Ks, Ms, 300, seed=9)
+    torch.cuda.synchronize()
+    so, wo, _, _ = rfi.layout(L, Ws)
+    stn = rfi.stats_numpy(st)
+    for s in range(6):
+        xs = xd[so[s]:so[s] + L[s]].cpu().numpy()
+        yo, sto = _oracle_stream(xs, s, Ws[s], Ks[s], Ms[s], 300, 9)
+        assert np.array_equal(y[so[s]:so[s] + L[s]].cpu().numpy(), yo), s
+        nw = (L[s] + Ws[s] - 1) // Ws[s]
+        assert np.array_equal(stn[wo[s]:wo[s] + nw], sto), s
+
+
+@pytest.mark.parametrize("mom_k", [1000, 4096])
+def test_large_carry_equals_whole_stream(gpu, mom_k):
+    # six noise streams in three calls of 3000 windows each (74 M samples
+    # per call): bytes and statistics equal one call over the whole streams
+    ns, W, nwc = 6, 4096, 3000
+    specs = [synth.StreamSpec(3 * nwc * W, W, 3.0, 2, 7.0 + 2 * i, 0.01, 8, 3000) for i in range(ns)]
+    L = [sp.length for sp in specs]
+    xd = synth.gen_packed(specs, 6, 43, device=gpu)
+    y_ref, st_ref = rfi.mom_filter(xd, L, [W] * ns, [3.0] * ns, [2] * ns, mom_k, seed=12)
+    so = rfi.layout(L, [W] * ns)[0]
+    hist = torch.zeros((ns, mom_k - 1), dtype=torch.uint8, device=gpu)
+    hlen = torch.zeros(ns, dtype=torch.int32, device=gpu)
+    n = nwc * W
+    for c in range(3):
+        xc = torch.cat([xd[so[s] + c * n:so[s] + (c + 1) * n] for s in range(ns)])
+        absb = torch.full((ns,), c * n, dtype=torch.int64, device=gpu)
+        yc, stc = rfi.mom_filter_carry(xc, [n] * ns, [W] * ns, [3.0] * ns, [2] * ns, mom_k, absb, hist, hlen,
+                                       seed=12)
+        for s in range(ns):
+            assert torch.equal(yc[s * n:(s + 1) * n], y_ref[so[s] + c * n:so[s] + (c + 1) * n]), (c, s)
+            assert torch.equal(stc[s * nwc:(s + 1) * nwc],
+                               st_ref[s * 3 * nwc + c * nwc:s * 3 * nwc + (c + 1) * nwc]), (c, s)
+    torch.cuda.synchronize()
+    assert hlen.cpu().tolist() == [mom_k - 1] * ns
