@@ -178,7 +178,7 @@ static hipError_t run_launch(const rfi_plan* p, const PlanLaunch& l, const Launc
     a.n_items = l.count;
     if (p->elem == 1) {
         if (l.kind == 0) return launch_i8_tiles(l.cls, l.modes, p->tpw > 0 ? p->tpw : tuned_tpw(plan_signature(p)), a, l.grid, s);
-        if (l.kind == 1) return launch_i8_generic(a, l.grid, s);
+        if (l.kind == 1) return launch_i8_generic(a, l.modes, l.grid, s);
         return launch_i8_fused(l.modes, a, l.grid, s);
     }
     if (l.kind == 0) return launch_i16_tiles(l.cls, a, l.grid, s);

@@ -127,7 +127,8 @@ __host__ __device__ inline StreamView resolve(const StreamDesc& d, const LaunchA
 // cls: tile class (-1 = generic items); modes: bit m set if mode m occurs;
 // fused: one kernel for all kinds.
 hipError_t launch_i8_tiles(int cls, int modes, int tpw, const LaunchArgs& a, int grid, hipStream_t s);
-hipError_t launch_i8_generic(const LaunchArgs& a, int grid, hipStream_t s);
+// modes: bit m set if some window of the launch uses mode m.
+hipError_t launch_i8_generic(const LaunchArgs& a, int modes, int grid, hipStream_t s);
 hipError_t launch_i8_fused(int modes, const LaunchArgs& a, int grid, hipStream_t s);
 hipError_t launch_i16_tiles(int cls, const LaunchArgs& a, int grid, hipStream_t s);
 hipError_t launch_i16_generic(const LaunchArgs& a, int grid, hipStream_t s);

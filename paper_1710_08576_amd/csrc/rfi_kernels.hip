@@ -719,9 +719,14 @@ __device__ __forceinline__ int noise_sample(int64_t j, uint64_t seed, uint32_t k
 // chunks byte by byte, so a neighbouring window's bytes are never written).
 constexpr int kGenericRegMin = 512;
 
+// NOISE: noise-mode windows qualify too, when each dword of the stream holds
+// one Philox block (absolute index of the stream's first sample a multiple
+// of 4).
+template <bool NOISE>
 __device__ __forceinline__ bool i8_generic_reg_ok(const StreamView& d, int64_t a, int n)
 {
-    if (d.head_len != 0 || d.mode == RFI_MODE_NOISE || n < kGenericRegMin) return false;
+    if (d.head_len != 0 || n < kGenericRegMin) return false;
+    if (d.mode == RFI_MODE_NOISE && (!NOISE || (d.abs_base & 3) != 0)) return false;
     if (((uintptr_t)d.x | (uintptr_t)d.y) & 15u) return false;
     // the last chunk may reach up to 15 bytes past the window: inside the
     // stream, or inside the packed layout's padding
@@ -731,7 +736,8 @@ __device__ __forceinline__ bool i8_generic_reg_ok(const StreamView& d, int64_t a
 
 __device__ __forceinline__ uint32_t byte_of(uint32_t v, int b) { return (v >> (8 * b)) & 0xFFu; }
 
-__device__ void i8_generic_reg(const StreamView& d, int64_t w, int64_t a, int n, GenericSmem& sm)
+template <bool NOISE>
+__device__ void i8_generic_reg(const StreamView& d, int64_t w, int64_t a, int n, uint64_t seed, GenericSmem& sm)
 {
     const int tid = (int)threadIdx.x, lane = lane_id(), wave = tid >> 6;
     const uint8_t* xb = static_cast<const uint8_t*>(d.x);
@@ -796,6 +802,30 @@ __device__ void i8_generic_reg(const StreamView& d, int64_t w, int64_t a, int n,
     const WinParams p = sm.prm;
     const uint32_t lo = rep_i16(p.lo * 256), hi = rep_i16(p.hi * 256);
     const uint32_t lo_u = rep_i16((p.lo + 128) * 256), hi_u = rep_i16((p.hi + 128) * 256);
+    bool noise = false;
+    if constexpr (NOISE) {
+        if (d.mode == RFI_MODE_NOISE) {
+            // One Philox block per dword holding a flagged sample, drawn in a
+            // loop over this lane's flagged dwords (one inlined draw).
+            noise = true;
+            uint32_t cf = 0;
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+                if (tid + (q >> 2) * kBlock < nch) cf |= ((clamp_i8x4(v[q], lo, hi) ^ v[q]) != 0 ? 1u : 0u) << q;
+            while (cf) {
+                const int q = __builtin_ctz(cf);
+                cf &= cf - 1;
+                uint32_t x = 0;
+#pragma unroll
+                for (int i = 0; i < 16; ++i) x = i == q ? v[i] : x;
+                const int64_t j0 = d.abs_base + (c0 + tid + (int64_t)(q >> 2) * kBlock) * 16 + 4 * (q & 3);
+                const uint32_t nz = noise_quad_i8((uint64_t)j0, seed, d.key, p.m, p.sq8);
+                x = byte_perm(nz, x, flag_sel_i8x4(x, lo_u, hi_u));
+#pragma unroll
+                for (int i = 0; i < 16; ++i) v[i] = i == q ? x : v[i];
+            }
+        }
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int64_t c = tid + k * kBlock;
@@ -806,7 +836,7 @@ __device__ void i8_generic_reg(const StreamView& d, int64_t w, int64_t a, int n,
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint32_t x = v[4 * k + j];
-            r[j] = clip ? clamp_i8x4(x, lo, hi) : byte_perm(0u, x, flag_sel_i8x4(x, lo_u, hi_u));
+            r[j] = noise ? x : clip ? clamp_i8x4(x, lo, hi) : byte_perm(0u, x, flag_sel_i8x4(x, lo_u, hi_u));
         }
         if (cb >= a && cb + 16 <= e) {
             gstore16_nt(yb + cb, make_uint4(r[0], r[1], r[2], r[3]));
@@ -820,14 +850,17 @@ __device__ void i8_generic_reg(const StreamView& d, int64_t w, int64_t a, int n,
 
 // REG: the register path is compiled in (kernels that may see zero or clip
 // windows).
-template <bool REG = true>
+// REG: zero/clip windows may take the register path; REG_NOISE: noise
+// windows too (kept out of the fused kernels, whose register budget the
+// inlined draw would raise).
+template <bool REG = true, bool REG_NOISE = false>
 __device__ void i8_generic(const StreamView& d, int64_t w, uint64_t seed, GenericSmem& sm)
 {
     const int W = d.window;
     const int64_t a = w * (int64_t)W;
     const int n = (int)min((int64_t)W, d.length - a);
-    if (REG && i8_generic_reg_ok(d, a, n)) {
-        i8_generic_reg(d, w, a, n, sm);
+    if (REG && i8_generic_reg_ok<REG_NOISE>(d, a, n)) {
+        i8_generic_reg<REG_NOISE>(d, w, a, n, seed, sm);
         return;
     }
     const int tid = (int)threadIdx.x;
@@ -1363,14 +1396,17 @@ __global__ __launch_bounds__(kBlock) void k_i8_tiles(LaunchArgs a)
     }
 }
 
-template <bool PERSIST>
+// NOISE: noise windows may take the register path (launched only for items
+// that include noise streams: the draw costs registers the other modes'
+// small windows would pay for in occupancy).
+template <bool PERSIST, bool NOISE>
 __global__ __launch_bounds__(kBlock) void k_i8_generic(LaunchArgs a)
 {
     __shared__ GenericSmem sm;
     for_items<PERSIST>(a, [&](int64_t it) {
         const Item item = a.items[it];
         const StreamView d = resolve(a.streams[item.stream], a);
-        i8_generic(d, item.first, a.seed, sm);
+        i8_generic<true, NOISE>(d, item.first, a.seed, sm);
     });
 }
 
@@ -1929,9 +1965,12 @@ hipError_t launch_i8_tiles(int cls, int modes, int tpw, const LaunchArgs& a, int
     return launch(k, a, persist ? grid : (int)((a.n_items + tpw - 1) / tpw), s);
 }
 #define RFI_PICK(K, a, grid) ((grid) < (a).n_items ? K<true> : K<false>)
-hipError_t launch_i8_generic(const LaunchArgs& a, int grid, hipStream_t s)
+hipError_t launch_i8_generic(const LaunchArgs& a, int modes, int grid, hipStream_t s)
 {
-    return launch(RFI_PICK(k_i8_generic, a, grid), a, grid, s);
+    const bool persist = grid < a.n_items;
+    void (*k)(LaunchArgs) = (modes & 4) ? (persist ? k_i8_generic<true, true> : k_i8_generic<false, true>)
+                                        : (persist ? k_i8_generic<true, false> : k_i8_generic<false, false>);
+    return launch(k, a, grid, s);
 }
 template <bool PERSIST>
 static void (*i8_fused_kernel(int modes))(LaunchArgs)
@@ -2070,7 +2109,7 @@ int persistent_grid(int elem_size, int cls, int modes, bool fused)
     void (*k)(LaunchArgs) = nullptr;
     if (elem_size == 1) {
         if (fused) k = i8_fused_kernel<true>(modes);
-        else if (cls < 0) k = k_i8_generic<true>;
+        else if (cls < 0) k = (modes & 4) ? k_i8_generic<true, true> : k_i8_generic<true, false>;
         else k = i8_tile_kernel(cls, modes, true, 1);
     } else {
         if (fused) k = k_i16_fused<true>;

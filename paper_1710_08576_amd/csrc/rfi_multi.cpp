@@ -171,7 +171,8 @@ int multi_execute(MultiPlan* p, const void* x, int8_t* const* y, rfi_window_stat
         a.stats_base = ma.stats_base[o];
         a.no_stats = ma.stats_base[o] == 0 ? 1 : 0;
         if (a.n_items > (1 << 30)) return RFI_ERR_INVALID;
-        hipError_t e = launch_i8_generic(a, (int)a.n_items, s);
+        // outputs with noise streams are single-output calls of their own
+        hipError_t e = launch_i8_generic(a, 3, (int)a.n_items, s);
         if (e != hipSuccess) return hip_fail(e);
     }
     return RFI_OK;

@@ -600,7 +600,7 @@ int rfi_server_flush(rfi_server* srv, uint32_t stream_id, void* out_dev, rfi_win
     a.n_items = 1;
     a.seed = srv->cfg.seed;
     set_wg_per_cu(0);
-    hipError_t e = srv->cfg.elem_size == 1 ? launch_i8_generic(a, 1, L.s) : launch_i16_generic(a, 1, L.s);
+    hipError_t e = srv->cfg.elem_size == 1 ? launch_i8_generic(a, 1 << st.mode, 1, L.s) : launch_i16_generic(a, 1, L.s);
     ++srv->n_launches;
     if (e == hipSuccess) e = hipStreamSynchronize(L.s);
     if (e != hipSuccess) return hip_fail(e);

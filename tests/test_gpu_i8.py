@@ -241,15 +241,15 @@ def test_autotune_picks_a_schedule_and_keeps_the_bytes(gpu):
 @pytest.mark.parametrize("W", [511, 512, 513, 1023, 1537, 3000, 8191, 16000, 16369, 16383])
 def test_generic_register_path_edges(gpu, W):
     """Generic windows around the register path's limits (512 samples, 1024
-    chunks) with window starts at every 16-byte phase, zero and clip mode,
+    chunks) with window starts at every 16-byte phase, all three modes,
     streams whose ends fall in the padding and a saturated, bimodal stream:
     equal to the oracle, no byte outside a window written (the sentinel
     padding of the helpers)."""
     rng = np.random.default_rng(W)
     specs = []
-    for i, mode in enumerate((rfi.ZERO, rfi.CLIP, rfi.ZERO, rfi.CLIP)):
+    for i, mode in enumerate((rfi.ZERO, rfi.CLIP, rfi.NOISE, rfi.CLIP, rfi.NOISE)):
         L = W * (3 + i) + int(rng.integers(1, 40))
-        specs.append(synth.StreamSpec(L, W, [2.0, 3.0, 4.0, 1.0][i], mode, 6.0 + 5 * i, 0.02, 4, 700))
+        specs.append(synth.StreamSpec(L, W, [2.0, 3.0, 4.0, 1.0, 2.5][i], mode, 6.0 + 5 * i, 0.02, 4, 700))
     x = synth.gen_packed(specs, seed=W, tag=9)
     # one stream of extremes: -128/127 halves, so the median and MAD sit at the ends
     so = rfi.layout([s.length for s in specs], [s.window for s in specs])[0]
