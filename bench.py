@@ -214,6 +214,24 @@ def main():
                                for k, v in ms16.items()}
         for p in plans16.values():
             p.close()
+        # W = 5000, not a tile class: every window through the generic
+        # kernel (register-resident, one window per workgroup).
+        st5, plans5, nw5 = setup(5000)
+        run_steps(plans5, x, y, st5, 2)
+        torch.cuda.synchronize()
+        ev5 = {m: ([], []) for m in (0, 1, 2)}
+        run_steps(plans5, x, y, st5, max(5, args.steps // 5), ev5)
+        torch.cuda.synchronize()
+        ab5 = algorithmic_bytes(n_samples, nw5)
+        out["window_5000_generic"] = {}
+        for m in (0, 1, 2):
+            v = float(np.median([a.elapsed_time(b) for a, b in zip(*ev5[m])]))
+            out["window_5000_generic"][MODE_NAMES[m]] = {
+                "ms": round(v, 4), "gsamples_s": round(n_samples / v / 1e6, 1),
+                "gb_s": round(ab5 / v / 1e6, 1), "roofline_frac": round(ab5 / v / 1e6 / HBM_PEAK_GBS, 4)}
+        for p in plans5.values():
+            p.close()
+        del st5
 
     if not args.no_batching:
         out["batching"] = bench_batching(args, dev)
