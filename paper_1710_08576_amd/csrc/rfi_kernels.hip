@@ -708,15 +708,15 @@ __device__ __forceinline__ int noise_sample(int64_t j, uint64_t seed, uint32_t k
     return (int)min(max((int64_t)m + q, (int64_t)vmin), (int64_t)vmax);
 }
 
-// Register path for a generic int8 window in zero or clip mode (or
-// statistics only) with no head segment, 16-byte aligned input and output,
-// and 512 <= n samples in at most 1024 16-byte chunks (noise windows take
-// the plain path, which keeps the draws out of this path's registers): the
-// aligned chunks covering [a, a + n) are loaded (four per lane),
-// their in-window bytes counted into per-wave replicated histograms, the
-// counts summed and selected as the wide tiles do, and the chunks replaced
-// in registers and stored (whole chunks as one 16-byte store, the two edge
-// chunks byte by byte, so a neighbouring window's bytes are never written).
+// Register path for a generic int8 window (zero, clip, statistics only,
+// and noise where the instance allows it) with no head segment, 16-byte
+// aligned input and output, and 512 <= n samples in at most 1024 16-byte
+// chunks: the aligned chunks covering [a, a + n) are loaded (four per
+// lane), their in-window bytes counted into per-wave replicated histograms,
+// the counts summed and selected as the wide tiles do, and the chunks
+// replaced in registers and stored (whole chunks as one 16-byte store, the
+// two edge chunks byte by byte, so a neighbouring window's bytes are never
+// written).
 constexpr int kGenericRegMin = 512;
 
 // NOISE: noise-mode windows qualify too, when each dword of the stream holds
