@@ -722,7 +722,7 @@ constexpr int kGenericRegMin = 512;
 // NOISE: noise-mode windows qualify too, when each dword of the stream holds
 // one Philox block (absolute index of the stream's first sample a multiple
 // of 4).
-template <bool NOISE>
+template <bool NOISE, int NT = kBlock>
 __device__ __forceinline__ bool i8_generic_reg_ok(const StreamView& d, int64_t a, int n)
 {
     if (d.head_len != 0 || n < kGenericRegMin) return false;
@@ -731,13 +731,15 @@ __device__ __forceinline__ bool i8_generic_reg_ok(const StreamView& d, int64_t a
     // the last chunk may reach up to 15 bytes past the window: inside the
     // stream, or inside the packed layout's padding
     if (!d.padded && ((a + n + 15) & ~(int64_t)15) > d.length) return false;
-    return ((a + n + 15) >> 4) - (a >> 4) <= 4 * kBlock;
+    return ((a + n + 15) >> 4) - (a >> 4) <= 4 * NT;
 }
 
 __device__ __forceinline__ uint32_t byte_of(uint32_t v, int b) { return (v >> (8 * b)) & 0xFFu; }
 
-template <bool NOISE>
-__device__ void i8_generic_reg(const StreamView& d, int64_t w, int64_t a, int n, uint64_t seed, GenericSmem& sm)
+// NT: threads of the workgroup (256, or 64 for windows of at most 256
+// chunks, so that more windows are in flight per CU).
+template <bool NOISE, int NT, class Smem>
+__device__ void i8_generic_reg(const StreamView& d, int64_t w, int64_t a, int n, uint64_t seed, Smem& sm)
 {
     const int tid = (int)threadIdx.x, lane = lane_id(), wave = tid >> 6;
     const uint8_t* xb = static_cast<const uint8_t*>(d.x);
@@ -747,7 +749,7 @@ __device__ void i8_generic_reg(const StreamView& d, int64_t w, int64_t a, int n,
     uint32_t v[16];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const int64_t c = tid + k * kBlock;
+        const int64_t c = tid + k * NT;
         uint4 t = make_uint4(0, 0, 0, 0);
         if (c < nch) t = gload16_nt(xb + (c0 + c) * 16);
         v[4 * k] = t.x;
@@ -758,12 +760,12 @@ __device__ void i8_generic_reg(const StreamView& d, int64_t w, int64_t a, int n,
     __syncthreads();  // the previous item is done with the scratch
     uint32_t* h = sm.whist + wave * kWaveHistWords;
     wide_hist_zero(h);
-    sm.tot[tid] = 0;
+    if constexpr (NT > 64) sm.tot[tid] = 0;
     __syncthreads();
     uint32_t* hl = h + (lane & 3) * kRepStride;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const int64_t c = tid + k * kBlock;
+        const int64_t c = tid + k * NT;
         if (c >= nch) continue;
         const int64_t cb = (c0 + c) * 16;
         if (cb >= a && cb + 16 <= e) {
@@ -778,15 +780,19 @@ __device__ void i8_generic_reg(const StreamView& d, int64_t w, int64_t a, int n,
     wave_sync();
     uint32_t cnt[4];
     wide_hist_totals(h, cnt);
+    if constexpr (NT > 64) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) atomicAdd(&sm.tot[lane * 4 + j], cnt[j]);
-    __syncthreads();
+        for (int j = 0; j < 4; ++j) atomicAdd(&sm.tot[lane * 4 + j], cnt[j]);
+        __syncthreads();
+        if (wave == 0) {
+            const uint4 t = *reinterpret_cast<const uint4*>(sm.tot + lane * 4);
+            cnt[0] = t.x;
+            cnt[1] = t.y;
+            cnt[2] = t.z;
+            cnt[3] = t.w;
+        }
+    }
     if (wave == 0) {
-        const uint4 t = *reinterpret_cast<const uint4*>(sm.tot + lane * 4);
-        cnt[0] = t.x;
-        cnt[1] = t.y;
-        cnt[2] = t.z;
-        cnt[3] = t.w;
         int mb, D;
         wide_select(cnt, sm.pc, (uint32_t)((n - 1) / 2 + 1), mb, D);
         WinParams p;
@@ -811,14 +817,14 @@ __device__ void i8_generic_reg(const StreamView& d, int64_t w, int64_t a, int n,
             uint32_t cf = 0;
 #pragma unroll
             for (int q = 0; q < 16; ++q)
-                if (tid + (q >> 2) * kBlock < nch) cf |= ((clamp_i8x4(v[q], lo, hi) ^ v[q]) != 0 ? 1u : 0u) << q;
+                if (tid + (q >> 2) * NT < nch) cf |= ((clamp_i8x4(v[q], lo, hi) ^ v[q]) != 0 ? 1u : 0u) << q;
             while (cf) {
                 const int q = __builtin_ctz(cf);
                 cf &= cf - 1;
                 uint32_t x = 0;
 #pragma unroll
                 for (int i = 0; i < 16; ++i) x = i == q ? v[i] : x;
-                const int64_t j0 = d.abs_base + (c0 + tid + (int64_t)(q >> 2) * kBlock) * 16 + 4 * (q & 3);
+                const int64_t j0 = d.abs_base + (c0 + tid + (int64_t)(q >> 2) * NT) * 16 + 4 * (q & 3);
                 const uint32_t nz = noise_quad_i8((uint64_t)j0, seed, d.key, p.m, p.sq8);
                 x = byte_perm(nz, x, flag_sel_i8x4(x, lo_u, hi_u));
 #pragma unroll
@@ -828,7 +834,7 @@ __device__ void i8_generic_reg(const StreamView& d, int64_t w, int64_t a, int n,
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const int64_t c = tid + k * kBlock;
+        const int64_t c = tid + k * NT;
         if (c >= nch) continue;
         const int64_t cb = (c0 + c) * 16;
         uint32_t r[4];
@@ -853,22 +859,22 @@ __device__ void i8_generic_reg(const StreamView& d, int64_t w, int64_t a, int n,
 // REG: zero/clip windows may take the register path; REG_NOISE: noise
 // windows too (kept out of the fused kernels, whose register budget the
 // inlined draw would raise).
-template <bool REG = true, bool REG_NOISE = false>
-__device__ void i8_generic(const StreamView& d, int64_t w, uint64_t seed, GenericSmem& sm)
+template <bool REG = true, bool REG_NOISE = false, int NT = kBlock, class Smem = GenericSmem>
+__device__ void i8_generic(const StreamView& d, int64_t w, uint64_t seed, Smem& sm)
 {
     const int W = d.window;
     const int64_t a = w * (int64_t)W;
     const int n = (int)min((int64_t)W, d.length - a);
-    if (REG && i8_generic_reg_ok<REG_NOISE>(d, a, n)) {
-        i8_generic_reg<REG_NOISE>(d, w, a, n, seed, sm);
+    if (REG && i8_generic_reg_ok<REG_NOISE, NT>(d, a, n)) {
+        i8_generic_reg<REG_NOISE, NT>(d, w, a, n, seed, sm);
         return;
     }
     const int tid = (int)threadIdx.x;
     int8_t* y = static_cast<int8_t*>(d.y);
     __syncthreads();
-    sm.hist[tid] = 0;
+    for (int i = tid; i < 256; i += NT) sm.hist[i] = 0;
     __syncthreads();
-    for (int i = tid; i < n; i += kBlock) atomicAdd(&sm.hist[load_logical<int8_t>(d, a + i) + 128], 1u);
+    for (int i = tid; i < n; i += NT) atomicAdd(&sm.hist[load_logical<int8_t>(d, a + i) + 128], 1u);
     __syncthreads();
     if (tid < 64) {
         int mb, D;
@@ -884,7 +890,7 @@ __device__ void i8_generic(const StreamView& d, int64_t w, uint64_t seed, Generi
     __syncthreads();
     if (d.mode == kModeStats) return;
     const WinParams p = sm.prm;
-    for (int i = tid; i < n; i += kBlock) {
+    for (int i = tid; i < n; i += NT) {
         const int x = load_logical<int8_t>(d, a + i);
         int yv = x;
         if (x < p.lo || x > p.hi) {
@@ -895,6 +901,18 @@ __device__ void i8_generic(const StreamView& d, int64_t w, uint64_t seed, Generi
         gstore(y + a + i, (int8_t)yv);
     }
 }
+
+// Scratch of the 64-thread generic kernel: one wave's replicated histogram
+// (or the plain histogram of the two-pass path), the cumulative counts and
+// the window's parameters (about 5.3 KB, so LDS admits 30 workgroups per CU).
+struct GenericSmem64 {
+    union {
+        uint32_t hist[256];
+        __align__(16) uint32_t whist[kWaveHistWords];
+    };
+    __align__(16) uint32_t pc[kPadC];
+    WinParams prm;
+};
 
 // ---------------------------------------------------------------------------
 // int16: radix select over two 8-bit digits.
@@ -1394,6 +1412,19 @@ __global__ __launch_bounds__(kBlock) void k_i8_tiles(LaunchArgs a)
         }
         write_stats(sa);
     }
+}
+
+// 64 threads per window, for launches whose windows all fit 256 chunks
+// (n <= 4066 at any alignment): up to 32 windows in flight per CU instead of
+// the 8 of the 256-thread kernel.  One item per workgroup.
+template <bool NOISE>
+__global__ __launch_bounds__(64) void k_i8_generic64(LaunchArgs a)
+{
+    __shared__ GenericSmem64 sm;
+    if ((int64_t)blockIdx.x >= a.n_items) return;
+    const Item item = a.items[blockIdx.x];
+    const StreamView d = resolve(a.streams[item.stream], a);
+    i8_generic<true, NOISE, 64>(d, item.first, a.seed, sm);
 }
 
 // NOISE: noise windows may take the register path (launched only for items
@@ -1965,9 +1996,16 @@ hipError_t launch_i8_tiles(int cls, int modes, int tpw, const LaunchArgs& a, int
     return launch(k, a, persist ? grid : (int)((a.n_items + tpw - 1) / tpw), s);
 }
 #define RFI_PICK(K, a, grid) ((grid) < (a).n_items ? K<true> : K<false>)
-hipError_t launch_i8_generic(const LaunchArgs& a, int modes, int grid, hipStream_t s)
+hipError_t launch_i8_generic(const LaunchArgs& a, int modes, int grid, hipStream_t s, bool small)
 {
     const bool persist = grid < a.n_items;
+    if (small && !persist) {
+        if (a.n_items <= 0) return hipSuccess;
+        if (a.n_items > (1 << 30)) return hipErrorInvalidValue;
+        if (modes & 4) hipLaunchKernelGGL(k_i8_generic64<true>, dim3((unsigned)a.n_items), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL(k_i8_generic64<false>, dim3((unsigned)a.n_items), dim3(64), 0, s, a);
+        return hipGetLastError();
+    }
     void (*k)(LaunchArgs) = (modes & 4) ? (persist ? k_i8_generic<true, true> : k_i8_generic<false, true>)
                                         : (persist ? k_i8_generic<true, false> : k_i8_generic<false, false>);
     return launch(k, a, grid, s);
