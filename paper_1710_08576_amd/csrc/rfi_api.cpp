@@ -112,7 +112,7 @@ struct PlanLaunch {
     int modes;  // bit m: some stream of the launch uses mode m
     int64_t first, count;
     int grid;
-    int small = 0;  // generic: every window spans at most 256 chunks (n <= 4066)
+    int small = 0;  // generic: 64 / 128 if every window spans at most 256 / 512 chunks
 };
 
 struct GraphEntry {
@@ -179,7 +179,7 @@ static hipError_t run_launch(const rfi_plan* p, const PlanLaunch& l, const Launc
     a.n_items = l.count;
     if (p->elem == 1) {
         if (l.kind == 0) return launch_i8_tiles(l.cls, l.modes, p->tpw > 0 ? p->tpw : tuned_tpw(plan_signature(p)), a, l.grid, s);
-        if (l.kind == 1) return launch_i8_generic(a, l.modes, l.grid, s, l.small != 0);
+        if (l.kind == 1) return launch_i8_generic(a, l.modes, l.grid, s, l.small);
         return launch_i8_fused(l.modes, a, l.grid, s);
     }
     if (l.kind == 0) return launch_i16_tiles(l.cls, a, l.grid, s);
@@ -231,13 +231,15 @@ static void build_launches(rfi_plan* p)
             }
             PlanLaunch l{g == 0 ? 1 : 0, 0, cls, modes, b, e - b, clamp_grid(e - b)};
             if (g == 0 && elem == 1) {
-                bool small = true;
-                for (int64_t i = b; i < e && small; ++i) {
+                // longest window of the launch; n + 30 <= 16 * 4 * NT keeps
+                // it within 4 * NT chunks at any alignment
+                int64_t nmax = 0;
+                for (int64_t i = b; i < e; ++i) {
                     const Item& it = p->hitems[i];
                     const int64_t w = p->W[it.stream];
-                    small = std::min<int64_t>(w, p->L[it.stream] - it.first * w) <= 4066;
+                    nmax = std::max<int64_t>(nmax, std::min<int64_t>(w, p->L[it.stream] - it.first * w));
                 }
-                l.small = small ? 1 : 0;
+                l.small = nmax <= 4066 ? 64 : nmax <= 8162 ? 128 : 0;
             }
             p->launches[RFI_SCHED_SPLIT].push_back(l);
             l.grid = (int)std::min<int64_t>(e - b, persistent_grid(elem, cls, l.modes, false));

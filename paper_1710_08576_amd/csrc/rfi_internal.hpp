@@ -128,9 +128,10 @@ __host__ __device__ inline StreamView resolve(const StreamDesc& d, const LaunchA
 // fused: one kernel for all kinds.
 hipError_t launch_i8_tiles(int cls, int modes, int tpw, const LaunchArgs& a, int grid, hipStream_t s);
 // modes: bit m set if some window of the launch uses mode m.
-// small: every window of the launch spans at most 256 16-byte chunks
-// (64-thread workgroups when the launch has one workgroup per item).
-hipError_t launch_i8_generic(const LaunchArgs& a, int modes, int grid, hipStream_t s, bool small = false);
+// small_nt: 64 or 128 if every window of the launch spans at most 4 x that
+// many 16-byte chunks (workgroups of that many threads when the launch has
+// one workgroup per item); 0: 256-thread workgroups.
+hipError_t launch_i8_generic(const LaunchArgs& a, int modes, int grid, hipStream_t s, int small_nt = 0);
 hipError_t launch_i8_fused(int modes, const LaunchArgs& a, int grid, hipStream_t s);
 hipError_t launch_i16_tiles(int cls, const LaunchArgs& a, int grid, hipStream_t s);
 hipError_t launch_i16_generic(const LaunchArgs& a, int grid, hipStream_t s);

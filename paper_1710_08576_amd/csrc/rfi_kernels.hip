@@ -760,7 +760,8 @@ __device__ void i8_generic_reg(const StreamView& d, int64_t w, int64_t a, int n,
     __syncthreads();  // the previous item is done with the scratch
     uint32_t* h = sm.whist + wave * kWaveHistWords;
     wide_hist_zero(h);
-    if constexpr (NT > 64) sm.tot[tid] = 0;
+    if constexpr (NT > 64)
+        for (int i = tid; i < 256; i += NT) sm.tot[i] = 0;
     __syncthreads();
     uint32_t* hl = h + (lane & 3) * kRepStride;
 #pragma unroll
@@ -902,14 +903,17 @@ __device__ void i8_generic(const StreamView& d, int64_t w, uint64_t seed, Smem& 
     }
 }
 
-// Scratch of the 64-thread generic kernel: one wave's replicated histogram
-// (or the plain histogram of the two-pass path), the cumulative counts and
-// the window's parameters (about 5.3 KB, so LDS admits 30 workgroups per CU).
-struct GenericSmem64 {
+// Scratch of the generic kernels with NW = 1 or 2 waves: their replicated
+// histograms (or the plain histogram of the two-pass path), the summed
+// counts (two waves), the cumulative counts and the window's parameters
+// (5.3 KB for one wave, so LDS admits 30 workgroups per CU; 10.6 KB for two).
+template <int NW>
+struct GenericSmemN {
     union {
         uint32_t hist[256];
-        __align__(16) uint32_t whist[kWaveHistWords];
+        __align__(16) uint32_t whist[NW * kWaveHistWords];
     };
+    __align__(16) uint32_t tot[NW > 1 ? 256 : 4];
     __align__(16) uint32_t pc[kPadC];
     WinParams prm;
 };
@@ -1414,17 +1418,18 @@ __global__ __launch_bounds__(kBlock) void k_i8_tiles(LaunchArgs a)
     }
 }
 
-// 64 threads per window, for launches whose windows all fit 256 chunks
-// (n <= 4066 at any alignment): up to 32 windows in flight per CU instead of
-// the 8 of the 256-thread kernel.  One item per workgroup.
-template <bool NOISE>
-__global__ __launch_bounds__(64) void k_i8_generic64(LaunchArgs a)
+// NT = 64 or 128 threads per window, for launches whose windows all fit
+// 4 * NT chunks (n <= 4066 or 8162 at any alignment): up to 30 or 15
+// windows in flight per CU instead of the 8 of the 256-thread kernel.  One
+// item per workgroup.
+template <int NT, bool NOISE>
+__global__ __launch_bounds__(NT) void k_i8_generic_small(LaunchArgs a)
 {
-    __shared__ GenericSmem64 sm;
+    __shared__ GenericSmemN<NT / 64> sm;
     if ((int64_t)blockIdx.x >= a.n_items) return;
     const Item item = a.items[blockIdx.x];
     const StreamView d = resolve(a.streams[item.stream], a);
-    i8_generic<true, NOISE, 64>(d, item.first, a.seed, sm);
+    i8_generic<true, NOISE, NT>(d, item.first, a.seed, sm);
 }
 
 // NOISE: noise windows may take the register path (launched only for items
@@ -1996,14 +2001,16 @@ hipError_t launch_i8_tiles(int cls, int modes, int tpw, const LaunchArgs& a, int
     return launch(k, a, persist ? grid : (int)((a.n_items + tpw - 1) / tpw), s);
 }
 #define RFI_PICK(K, a, grid) ((grid) < (a).n_items ? K<true> : K<false>)
-hipError_t launch_i8_generic(const LaunchArgs& a, int modes, int grid, hipStream_t s, bool small)
+hipError_t launch_i8_generic(const LaunchArgs& a, int modes, int grid, hipStream_t s, int small_nt)
 {
     const bool persist = grid < a.n_items;
-    if (small && !persist) {
+    if ((small_nt == 64 || small_nt == 128) && !persist) {
         if (a.n_items <= 0) return hipSuccess;
         if (a.n_items > (1 << 30)) return hipErrorInvalidValue;
-        if (modes & 4) hipLaunchKernelGGL(k_i8_generic64<true>, dim3((unsigned)a.n_items), dim3(64), 0, s, a);
-        else hipLaunchKernelGGL(k_i8_generic64<false>, dim3((unsigned)a.n_items), dim3(64), 0, s, a);
+        const bool noise = (modes & 4) != 0;
+        void (*k)(LaunchArgs) = small_nt == 64 ? (noise ? k_i8_generic_small<64, true> : k_i8_generic_small<64, false>)
+                                               : (noise ? k_i8_generic_small<128, true> : k_i8_generic_small<128, false>);
+        hipLaunchKernelGGL(k, dim3((unsigned)a.n_items), dim3((unsigned)small_nt), 0, s, a);
         return hipGetLastError();
     }
     void (*k)(LaunchArgs) = (modes & 4) ? (persist ? k_i8_generic<true, true> : k_i8_generic<false, true>)
