@@ -238,7 +238,11 @@ def test_autotune_picks_a_schedule_and_keeps_the_bytes(gpu):
     q.close()
 
 
-@pytest.mark.parametrize("W", [511, 512, 513, 1023, 1537, 3000, 8191, 16000, 16369, 16383])
+# 4066 / 4067 and 8162 / 8163: the longest windows of the 64- and 128-thread
+# generic workgroups and the first past them; 4081 / 4082 and 8177 / 8178:
+# the most chunks those workgroups can hold at some phase
+@pytest.mark.parametrize("W", [511, 512, 513, 1023, 1537, 3000, 4066, 4067, 4081, 4082, 8162, 8163, 8177,
+                               8178, 8191, 16000, 16369, 16383])
 def test_generic_register_path_edges(gpu, W):
     """Generic windows around the register path's limits (512 samples, 1024
     chunks) with window starts at every 16-byte phase, all three modes,
