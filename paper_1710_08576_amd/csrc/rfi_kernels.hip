@@ -710,9 +710,9 @@ __device__ __forceinline__ int noise_sample(int64_t j, uint64_t seed, uint32_t k
 
 // Register path for a generic int8 window (zero, clip, statistics only,
 // and noise where the instance allows it) with no head segment, 16-byte
-// aligned input and output, and 512 <= n samples in at most 1024 16-byte
-// chunks: the aligned chunks covering [a, a + n) are loaded (four per
-// lane), their in-window bytes counted into per-wave replicated histograms,
+// aligned input and output, and 512 <= n samples in at most four 16-byte
+// chunks per thread: the aligned chunks covering [a, a + n) are loaded (four
+// per lane), their in-window bytes counted into per-wave replicated histograms,
 // the counts summed and selected as the wide tiles do, and the chunks
 // replaced in registers and stored (whole chunks as one 16-byte store, the
 // two edge chunks byte by byte, so a neighbouring window's bytes are never
@@ -736,8 +736,8 @@ __device__ __forceinline__ bool i8_generic_reg_ok(const StreamView& d, int64_t a
 
 __device__ __forceinline__ uint32_t byte_of(uint32_t v, int b) { return (v >> (8 * b)) & 0xFFu; }
 
-// NT: threads of the workgroup (256, or 64 for windows of at most 256
-// chunks, so that more windows are in flight per CU).
+// NT: threads of the workgroup (256, or 64 / 128 for launches whose windows
+// span at most 256 / 512 chunks, so that more windows are in flight per CU).
 template <bool NOISE, int NT, class Smem>
 __device__ void i8_generic_reg(const StreamView& d, int64_t w, int64_t a, int n, uint64_t seed, Smem& sm)
 {
