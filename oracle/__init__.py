@@ -8,8 +8,8 @@ The arithmetic lives in ``rfi_oracle.c`` (plain C, full sort per window);
 this module only builds it with gcc and marshals numpy arrays through ctypes.
 Paper: Buch et al., "Implementing and Characterizing Real-time Broadband RFI
 Excision for the GMRT Wideband Backend", Sec. II-D, Eqs. (1)-(3); the
-improvement metric of Sec. III-A (block power, mean-to-RMS ratio,
-improvement in dB) is plain numpy at the end of this module.
+improvement metric of Sec. III-A (block power, the ratio S, improvement
+in dB) is plain numpy at the end of this module.
 """
 from __future__ import annotations
 
@@ -168,9 +168,12 @@ def mom_filter_batch(x, lengths, windows, k, mode, mom_k: int, seed: int = 0,
 
 
 # ---------------------------------------------------------------------------
-# Improvement metric (Sec. III-A): the filter's effect is scored as
-# 10 log10 of the ratio of the average mean-to-RMS ratios of the filtered
-# and unfiltered integrated power.  Plain numpy, integers exact, ratios fp64.
+# Improvement metric (Sec. III-A): a filter's score in dB is ten times the
+# base-10 logarithm of S before filtering (S_U) over S after it (S_F), S being
+# a figure relating the mean of the integrated power to its RMS.  Its defining
+# source is not available; the reading taken here (per segment, RMS deviation
+# over mean, averaged) is stated in s_ratio.  Plain numpy, integers exact,
+# ratios fp64.
 # ---------------------------------------------------------------------------
 
 def block_power(x, lengths, block: int) -> np.ndarray:
@@ -190,13 +193,16 @@ def block_power(x, lengths, block: int) -> np.ndarray:
     return np.array(out, dtype=np.int64)
 
 
-def mean_to_rms(power, seg: int) -> float:
-    """Average mean-to-RMS ratio (Sec. III-A), read as: the average over
-    consecutive segments of ``seg`` values of the ratio of
-    the segment's mean to its RMS deviation about that mean (population
-    form).  Values after the last whole segment are not used; no whole
-    segment gives NaN.  A segment with no deviation gives +inf (or NaN when
-    its mean is 0 too), as IEEE division does."""
+def s_ratio(power, seg: int) -> float:
+    """S of Sec. III-A (the paper's "average mean-to-RMS ratio"), read as
+    the average, over consecutive segments of ``seg`` values, of the
+    segment's RMS deviation about its mean (population form) divided by
+    that mean.  This orientation is the one under which the printed
+    improvement 10 log10(S_U / S_F) is positive when filtering steadies the
+    integrated power; the mean over RMS would make every improvement the
+    paper reports negative.  Values after the last whole segment are not
+    used; no whole segment gives NaN.  A segment with no deviation gives 0
+    (NaN when its mean is 0 too), as IEEE division does."""
     p = np.asarray(power, dtype=np.float64)
     n_seg = len(p) // seg
     if n_seg == 0:
@@ -207,25 +213,24 @@ def mean_to_rms(power, seg: int) -> float:
         mu = v.sum() / seg
         rms = np.sqrt(((v - mu) ** 2).sum() / seg)
         with np.errstate(divide="ignore", invalid="ignore"):
-            ratios.append(np.float64(mu) / np.float64(rms))
+            ratios.append(np.float64(rms) / np.float64(mu))
     return float(np.sum(ratios) / n_seg)
 
 
 def improvement(power_u, power_f, lengths, block: int, seg: int) -> np.ndarray:
-    """Improvement metric (Sec. III-A), per stream (S_U, S_F, I): the
-    average mean-to-RMS ratios of the
-    unfiltered and filtered block powers (whole blocks only) and the
-    improvement I = 10 log10(S_F / S_U) in dB (positive when filtering
-    steadies the integrated power).  ``power_*`` as from block_power."""
+    """Improvement metric (Sec. III-A), per stream (S_U, S_F, I): S (see
+    s_ratio) of the unfiltered and filtered block powers (whole blocks
+    only) and the improvement I = 10 log10(S_U / S_F) in dB, as printed.
+    ``power_*`` as from block_power."""
     out = np.zeros((len(lengths), 3), dtype=np.float64)
     off = 0
     for s, L in enumerate(lengths):
         L = int(L)
         nb = (L + block - 1) // block
         full = L // block
-        su = mean_to_rms(np.asarray(power_u)[off:off + full], seg)
-        sf = mean_to_rms(np.asarray(power_f)[off:off + full], seg)
+        su = s_ratio(np.asarray(power_u)[off:off + full], seg)
+        sf = s_ratio(np.asarray(power_f)[off:off + full], seg)
         with np.errstate(divide="ignore", invalid="ignore"):
-            out[s] = (su, sf, 10.0 * np.log10(np.float64(sf) / np.float64(su)))
+            out[s] = (su, sf, 10.0 * np.log10(np.float64(su) / np.float64(sf)))
         off += nb
     return out

@@ -43,40 +43,50 @@ def test_block_power_closed_forms():
     assert oracle.block_power(big, [8], 8).tolist() == [8 << 30]
 
 
-# ------------------------------------------------------- mean-to-RMS, metric
+# --------------------------------------------------------- the ratio S, metric
 
-def test_mean_to_rms_two_level_closed_form():
-    # a series alternating a, b: mean (a + b) / 2, RMS deviation |a - b| / 2
-    for a, b in ((10, 30), (5, 6), (1000, 1)):
-        assert oracle.mean_to_rms([a, b] * 8, 16) == pytest.approx((a + b) / abs(a - b), rel=1e-15)
-    # averaging over segments: two segments with ratios 2 and 10
-    s = oracle.mean_to_rms([10, 30] * 4 + [18, 22] * 4, 8)
-    assert s == pytest.approx(6.0, rel=1e-15)
+def test_s_ratio_two_level_closed_form():
+    # a series alternating a, b: mean (a + b) / 2, RMS deviation |a - b| / 2,
+    # so S = |a - b| / (a + b) (worked by hand, not from the code)
+    for a, b, want in ((10, 30, 0.5), (5, 6, 1 / 11), (1000, 1, 999 / 1001)):
+        assert oracle.s_ratio([a, b] * 8, 16) == pytest.approx(want, rel=1e-15)
+    # averaging over segments: two segments with ratios 0.5 and 0.1
+    s = oracle.s_ratio([10, 30] * 4 + [18, 22] * 4, 8)
+    assert s == pytest.approx(0.3, rel=1e-15)
     # trailing values beyond the last whole segment are ignored
-    assert oracle.mean_to_rms([10, 30] * 4 + [1e9], 8) == pytest.approx(2.0, rel=1e-15)
-    assert np.isnan(oracle.mean_to_rms([1, 2, 3], 4))
-    assert oracle.mean_to_rms([5, 5, 5, 5], 4) == np.inf
+    assert oracle.s_ratio([10, 30] * 4 + [1e9], 8) == pytest.approx(0.5, rel=1e-15)
+    assert np.isnan(oracle.s_ratio([1, 2, 3], 4))
+    # no deviation: S = 0; no deviation and zero mean: 0 / 0
+    assert oracle.s_ratio([5, 5, 5, 5], 4) == 0.0
+    assert np.isnan(oracle.s_ratio([0, 0, 0, 0], 4))
+    # a steadier series has the smaller S
+    assert oracle.s_ratio([19, 21] * 8, 16) < oracle.s_ratio([10, 30] * 8, 16)
 
 
-def test_mean_to_rms_gaussian_power():
+def test_s_ratio_gaussian_power():
     # P = sum of N squared N(0, sigma^2) samples: mean N sigma^2, standard
-    # deviation sigma^2 sqrt(2N), so the ratio is sqrt(N / 2) (rounding to
-    # integers moves it by well under 1 % at sigma 10).
+    # deviation sigma^2 sqrt(2N), so S = sqrt(2 / N) (rounding to integers
+    # moves it by well under 1 % at sigma 10).
     N, nb = 4096, 1024
     g = np.random.default_rng(11)
     x = np.clip(np.round(g.normal(0, 10.0, N * nb)), -128, 127).astype(np.int8)
     p = oracle.block_power(x, [N * nb], N)
-    s = oracle.mean_to_rms(p, 256)
-    assert s == pytest.approx(np.sqrt(N / 2), rel=0.08)
+    s = oracle.s_ratio(p, 256)
+    assert s == pytest.approx(np.sqrt(2 / N), rel=0.08)
 
 
 def test_improvement_hand_example_and_invariances():
+    # worked by hand: S_U = 20 / 40 = 0.5, S_F = 4 / 40 = 0.1, and the printed
+    # 10 log10(S_U / S_F) = 10 log10 5 = +6.9897 dB: the steadier filtered
+    # power scores a positive improvement.
     L, block = 16 * 5, 5
     pu = np.array([10, 30] * 8, dtype=np.int64)
     pf = np.array([18, 22] * 8, dtype=np.int64)
     r = oracle.improvement(pu, pf, [L], block, 16)[0]
-    assert r[0] == pytest.approx(2.0) and r[1] == pytest.approx(10.0)
-    assert r[2] == pytest.approx(10 * np.log10(5.0), abs=1e-12)
+    assert r[0] == pytest.approx(0.5, rel=1e-15) and r[1] == pytest.approx(0.1, rel=1e-15)
+    assert r[2] == pytest.approx(6.989700043360188, abs=1e-12)
+    # swapping the two inputs flips the sign
+    assert oracle.improvement(pf, pu, [L], block, 16)[0][2] == pytest.approx(-6.989700043360188, abs=1e-12)
     # identical series: 0 dB; a constant gain on the filtered power: 0 dB
     assert oracle.improvement(pu, pu, [L], block, 16)[0][2] == 0.0
     assert oracle.improvement(pu, 4 * pu, [L], block, 16)[0][2] == pytest.approx(0.0, abs=1e-12)
@@ -85,6 +95,9 @@ def test_improvement_hand_example_and_invariances():
     pf2 = np.concatenate([pf, [1]])
     r2 = oracle.improvement(pu2, pf2, [L + 3], block, 16)[0]
     assert r2.tolist() == r.tolist()
+    # a stream with no whole segment: NaN throughout
+    r3 = oracle.improvement(pu[:10], pf[:10], [50], block, 16)[0]
+    assert np.all(np.isnan(r3))
 
 
 def test_replacement_ranking_on_synthetic_bursts():
