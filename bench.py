@@ -425,8 +425,9 @@ def bench_multi(args, dev, x, L):
 def bench_improvement(args, dev, x, y, L):
     """Improvement metric (Sec. III-A) of each replacement mode on the
     plain-scale batch (W 4096, k 3): power integrated over blocks of 2^20
-    samples (1.31 ms at 800 Msample/s, the beamformer's 1.3 ms), mean-to-RMS
-    ratios over segments of 16 blocks, 10 log10(S_F / S_U) per stream."""
+    samples (1.31 ms at 800 Msample/s, the beamformer's 1.3 ms), S = RMS
+    deviation over mean averaged over segments of 16 blocks, and the printed
+    improvement 10 log10(S_U / S_F) per stream."""
     import numpy as np
     import torch
 
@@ -455,7 +456,7 @@ def bench_improvement(args, dev, x, y, L):
         r = rfi.improvement(pu, pf, L, block, seg, out=res).cpu().numpy()
         out[name + "_db"] = {"median": round(float(np.median(r[:, 2])), 2), "min": round(float(r[:, 2].min()), 2),
                              "max": round(float(r[:, 2].max()), 2)}
-    out["s_unfiltered_median"] = round(float(np.median(r[:, 0])), 2)
+    out["s_unfiltered_median"] = round(float(np.median(r[:, 0])), 5)
     return out
 
 

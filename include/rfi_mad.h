@@ -143,17 +143,20 @@ const char* rfi_status_string(int status);
 int rfi_block_power(const void* x, int32_t elem_bytes, int32_t n_streams, const int64_t* lengths,
                     int32_t block, int64_t* power_out, void* stream);
 
-/* Improvement metric (Sec. III-A) from the block powers of an unfiltered
- * (power_u) and a filtered (power_f) batch, both laid out as rfi_block_power
- * writes them for the same lengths and block.  Per stream, over its whole
- * blocks only (a short final block is not used): the values are cut into
- * floor(whole_blocks / seg_blocks) segments of seg_blocks consecutive blocks
- * (the rest is not used); a segment's mean-to-RMS ratio is its mean over
- * the population RMS of its deviations from that mean; S is the average of
- * those ratios.  out[3 s + 0] = S_U, out[3 s + 1] = S_F,
- * out[3 s + 2] = 10 log10(S_F / S_U) in dB (positive when the filtered power
- * is steadier), binary64 on the device (device buffer, 8-byte aligned).
- * No whole segment: NaN; a segment without deviation: +inf (IEEE division).
+/* Improvement metric (Sec. III-A), which the paper gives in dB as
+ * 10 log10(S_U / S_F) of a figure S relating the mean of the integrated
+ * power to its RMS, unfiltered (U) and filtered (F).  Inputs are the block
+ * powers of an unfiltered (power_u) and a filtered (power_f) batch, both
+ * laid out as rfi_block_power writes them for the same lengths and block.
+ * Per stream, over its whole blocks only (a short final block is not used):
+ * the values are cut into floor(whole_blocks / seg_blocks) segments of
+ * seg_blocks consecutive blocks (the rest is not used); S is the average
+ * over segments of the segment's population RMS deviation about its mean
+ * divided by that mean.  out[3 s + 0] = S_U, out[3 s + 1] = S_F,
+ * out[3 s + 2] = 10 log10(S_U / S_F) in dB (positive when the filtered
+ * power is steadier), binary64 on the device (device buffer, 8-byte
+ * aligned).  No whole segment: NaN; a segment without deviation adds 0 to
+ * S (IEEE division; 0 / 0 = NaN for an all-zero segment).
  * seg_blocks >= 1.  Errors as rfi_block_power.  Asynchronous on `stream`. */
 int rfi_improvement(const int64_t* power_u, const int64_t* power_f, int32_t n_streams, const int64_t* lengths,
                     int32_t block, int32_t seg_blocks, double* out, void* stream);

@@ -510,8 +510,10 @@ def block_power(x, lengths, block: int, out=None, stream=None):
 
 
 def improvement(power_u, power_f, lengths, block: int, seg_blocks: int, out=None, stream=None):
-    """Per stream (S_U, S_F, I dB) from unfiltered and filtered block powers
-    (Sec. III-A improvement metric); returns a float64 [n_streams, 3] tensor."""
+    """Per stream (S_U, S_F, I = 10 log10(S_U / S_F) dB) from unfiltered and
+    filtered block powers (Sec. III-A improvement metric; S = average over
+    segments of RMS deviation over mean); returns a float64 [n_streams, 3]
+    tensor."""
     import torch
     L = np.ascontiguousarray(lengths, dtype=np.int64)
     if out is None:

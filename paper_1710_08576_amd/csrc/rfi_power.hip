@@ -1,15 +1,17 @@
 // rfi_power.hip -- the improvement metric of Sec. III-A on the device.
 //
-// The paper scores a filter by 10 log10 of a ratio of average mean-to-RMS
-// ratios of the integrated power of the unfiltered and filtered signals.
-// Here the power is integrated over blocks of consecutive time samples:
+// The paper scores a filter in dB as ten times the base-10 logarithm of
+// S_U / S_F, S relating the mean of the integrated power to its RMS, before
+// (U) and after (F) filtering.  Here the power is integrated over blocks of
+// consecutive time samples:
 //
 //   rfi_block_power   P[s][b] = sum of x^2 over block b of stream s (exact,
 //                     int64), one read of the samples;
-//   rfi_improvement   per stream, the average over segments of seg_blocks
-//                     whole blocks of (segment mean) / (RMS deviation about
-//                     it), for the unfiltered and the filtered powers, and
-//                     I = 10 log10(S_F / S_U) (binary64).
+//   rfi_improvement   per stream, S = the average over segments of
+//                     seg_blocks whole blocks of (RMS deviation about the
+//                     segment mean) / (segment mean), for the unfiltered and
+//                     the filtered powers, and I = 10 log10(S_U / S_F)
+//                     (binary64; positive when filtering steadies the power).
 //
 // Block power is HBM-bound (1 or 2 B per sample read, 8 B per block
 // written).  A workgroup sums one part of at most 64 KiB of one block with
@@ -177,10 +179,11 @@ __global__ __launch_bounds__(kPowBlock) void k_block_power_sum(const PowRow* row
     gstore(power + g, t);
 }
 
-// Average mean-to-RMS ratio of n_seg segments of seg consecutive values:
-// per segment two passes (mean, then squared deviations) in binary64, each
-// thread a strided set of segments, then a fixed-shape tree over threads.
-__device__ double mean_to_rms_avg(const int64_t* p, int64_t n_seg, int32_t seg, double* red)
+// S of n_seg segments of seg consecutive values: per segment two passes
+// (mean, then squared deviations) in binary64, the segment's RMS deviation
+// over its mean, each thread a strided set of segments, then the average by
+// a fixed-shape tree over threads.
+__device__ double s_ratio_avg(const int64_t* p, int64_t n_seg, int32_t seg, double* red)
 {
     const int tid = (int)threadIdx.x;
     double acc = 0.0;
@@ -194,7 +197,7 @@ __device__ double mean_to_rms_avg(const int64_t* p, int64_t n_seg, int32_t seg, 
             const double d = (double)v[i] - mu;
             dev += d * d;
         }
-        acc += mu / sqrt(dev / (double)seg);
+        acc += sqrt(dev / (double)seg) / mu;
     }
     red[tid] = acc;
     __syncthreads();
@@ -219,13 +222,13 @@ __global__ __launch_bounds__(kPowBlock) void k_improvement(const PowRow* rows, i
     if (n_seg == 0) {
         su = sf = __builtin_nan("");
     } else {
-        su = mean_to_rms_avg(pu + r.block_begin, n_seg, seg, red);
-        sf = mean_to_rms_avg(pf + r.block_begin, n_seg, seg, red);
+        su = s_ratio_avg(pu + r.block_begin, n_seg, seg, red);
+        sf = s_ratio_avg(pf + r.block_begin, n_seg, seg, red);
     }
     if (threadIdx.x == 0) {
         gstore(out + 3 * s, su);
         gstore(out + 3 * s + 1, sf);
-        gstore(out + 3 * s + 2, 10.0 * log10(sf / su));
+        gstore(out + 3 * s + 2, 10.0 * log10(su / sf));
     }
 }
 

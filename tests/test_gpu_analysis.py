@@ -100,14 +100,18 @@ def test_improvement_matches_oracle(gpu, seg):
 def test_improvement_closed_forms(gpu):
     pu = torch.tensor([10, 30] * 8, dtype=torch.int64, device=gpu)
     pf = torch.tensor([18, 22] * 8, dtype=torch.int64, device=gpu)
+    # hand-worked: S_U = 20 / 40, S_F = 4 / 40, 10 log10(S_U / S_F) = 10 log10 5
     r = rfi.improvement(pu, pf, [80], 5, 16).cpu().numpy()[0]
-    assert r[0] == pytest.approx(2.0, rel=1e-15) and r[1] == pytest.approx(10.0, rel=1e-15)
-    assert r[2] == pytest.approx(10 * np.log10(5.0), abs=1e-12)
+    assert r[0] == pytest.approx(0.5, rel=1e-15) and r[1] == pytest.approx(0.1, rel=1e-15)
+    assert r[2] == pytest.approx(6.989700043360188, abs=1e-12)
+    r = rfi.improvement(pf, pu, [80], 5, 16).cpu().numpy()[0]
+    assert r[2] == pytest.approx(-6.989700043360188, abs=1e-12)
     r = rfi.improvement(pu, pu, [80], 5, 16).cpu().numpy()[0]
     assert r[2] == 0.0
+    # a filtered power with no deviation: S_F = 0, improvement +inf
     const = torch.full((16,), 7, dtype=torch.int64, device=gpu)
-    r = rfi.improvement(const, pu, [80], 5, 16).cpu().numpy()[0]
-    assert r[0] == np.inf
+    r = rfi.improvement(pu, const, [80], 5, 16).cpu().numpy()[0]
+    assert r[1] == 0.0 and r[2] == np.inf
 
 
 def test_improvement_ranking_plain_scale_full_size(gpu):
