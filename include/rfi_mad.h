@@ -221,6 +221,30 @@ int rfi_mom_filter_carry(const int8_t* x, int8_t* y, int32_t n_streams, const in
                          uint64_t seed, const int64_t* abs_base, uint8_t* mad_history, int32_t* history_len,
                          rfi_window_stats* stats_out, void* stream);
 
+/* rfi_mad_filter without allocation, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight real-time loops,
+ * harnesses that forbid hipMalloc.  Arguments, layout, results (bit for
+ * bit), asynchrony and argument errors are those of rfi_mad_filter.  The
+ * call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine, no host-to-device copy): the per-stream descriptors and the
+ * work items it would keep in a plan are written by a device kernel into
+ * a fixed array of 4 MiB in device memory that each GPU holds from the
+ * first call on it until the process ends.
+ * Limits (else RFI_ERR_UNSUPPORTED, nothing enqueued):
+ *   n_streams <= RFI_NOALLOC_MAX_STREAMS, and at most RFI_NOALLOC_MAX_ITEMS
+ *   work items, counted per stream as: W in {512, 1024, 2048, 4096, 8192,
+ *   16384}: floor(L / 16384) + ceil(L / W) - floor(L / 16384) * (16384 / W);
+ *   any other W: ceil(L / W).
+ * Every call on one GPU rewrites that GPU's array: calls that overlap on
+ * one GPU (from two host threads, or on two HIP streams the caller does
+ * not order) race and give undefined results; calls ordered on one stream,
+ * or on different GPUs, do not. */
+#define RFI_NOALLOC_MAX_STREAMS 1024
+#define RFI_NOALLOC_MAX_ITEMS 257536
+int rfi_mad_filter_noalloc(const int8_t* x, int8_t* y, int32_t n_streams, const int64_t* lengths,
+                           const int32_t* windows, const float* k, const int32_t* mode, uint64_t seed,
+                           rfi_window_stats* stats_out, void* stream);
+
 /* ------------------------------------------------------------------ */
 /* Explicit plans: a work table for one argument signature, reusable   */
 /* across calls, with a selectable launch schedule and HIP-graph       */

@@ -52,6 +52,7 @@ PP = ctypes.POINTER(ctypes.c_void_p)
 _SIGS = {
     "rfi_mad_filter": (ctypes.c_int, [P, P, I32, P, P, P, P, U64, P, P]),
     "rfi_mad_filter_i16": (ctypes.c_int, [P, P, I32, P, P, P, P, U64, P, P]),
+    "rfi_mad_filter_noalloc": (ctypes.c_int, [P, P, I32, P, P, P, P, U64, P, P]),
     "rfi_mom_filter": (ctypes.c_int, [P, P, I32, P, P, P, P, I32, U64, P, P]),
     "rfi_mom_filter_carry": (ctypes.c_int, [P, P, I32, P, P, P, P, I32, U64, P, P, P, P, P]),
     "rfi_mad_filter_multi": (ctypes.c_int, [P, I32, P, I32, P, P, P, P, U64, P, P]),
@@ -209,6 +210,25 @@ def mad_filter(x, lengths, windows, k, mode, seed: int = 0, y=None, stats=True, 
            _stream_handle(stream))
     _check(rc, "rfi_mad_filter")
     return y, (st[:nw] if st is not None else None)
+
+
+def mad_filter_noalloc(x, lengths, windows, k, mode, seed: int = 0, y=None, stats=None, stream=None):
+    """rfi_mad_filter_noalloc: int8 filtering with the library's fixed
+    per-device tables (no allocation in the library).  y and stats (int32
+    [n_windows, 4]) are caller buffers; when omitted they are allocated
+    here, by torch, before the call.  Returns (y, stats)."""
+    import torch
+    n = len(lengths)
+    L = np.ascontiguousarray(lengths, dtype=np.int64)
+    W, K, M = _arr(windows, np.int32, n), _arr(k, np.float32, n), _arr(mode, np.int32, n)
+    if x.dtype != torch.int8:
+        raise TypeError("x must be int8")
+    if y is None:
+        y = torch.empty_like(x)
+    rc = load().rfi_mad_filter_noalloc(_tptr(x), _tptr(y), n, _ptr(L), _ptr(W), _ptr(K), _ptr(M), seed,
+                                       _tptr(stats), _stream_handle(stream))
+    _check(rc, "rfi_mad_filter_noalloc")
+    return y, stats
 
 
 def mad_filter_multi(x, lengths, windows, ks, modes, seed: int = 0, ys=None, stats=True, stream=None):

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "librfimad.so")
 SOURCES = ["rfi_kernels.hip", "rfi_ubench.hip", "rfi_api.cpp", "rfi_serve.cpp", "rfi_mom.cpp", "rfi_multi.cpp",
-           "rfi_power.hip"]
+           "rfi_power.hip", "rfi_noalloc.hip"]
 ARCH = os.environ.get("RFI_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
