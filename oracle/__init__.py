@@ -41,6 +41,12 @@ def build() -> str:
 _lib = None
 
 
+def default_threads() -> int:
+    """Host threads for the batch calls: all cores, at most 16 (a GPU machine
+    grants one GPU's share of its CPUs, whatever the core count shows)."""
+    return max(1, min(os.cpu_count() or 1, 16))
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -134,7 +140,7 @@ def filter_batch(x, lengths, windows, k, mode, seed: int = 0, n_threads: int | N
     st = np.zeros(max(total, 1), dtype=STATS_DTYPE)
     f = lib().orc_filter_i8 if x.dtype == np.int8 else lib().orc_filter_i16
     if n_threads is None:
-        n_threads = os.cpu_count() or 1
+        n_threads = default_threads()
     rc = f(_ptr(x), _ptr(y), n, _ptr(L), _ptr(W), _ptr(K), _ptr(M), seed, _ptr(st), n_threads)
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
@@ -159,7 +165,7 @@ def mom_filter_batch(x, lengths, windows, k, mode, mom_k: int, seed: int = 0,
     y = x.copy()
     st = np.zeros(max(total, 1), dtype=STATS_DTYPE)
     if n_threads is None:
-        n_threads = os.cpu_count() or 1
+        n_threads = default_threads()
     rc = lib().orc_mom_filter_i8(_ptr(x), _ptr(y), n, _ptr(L), _ptr(W), _ptr(K), _ptr(M),
                                  int(mom_k), seed, _ptr(st), n_threads)
     if rc != 0:
