@@ -175,6 +175,99 @@ def write_markdown(summary, out):
         f.write("\n".join(lines) + "\n")
 
 
+def counter_passes(dirs):
+    """{kernel: {counter: mean value per dispatch}} over counter-pass dirs."""
+    per = {}
+    for d in dirs:
+        for r in _csv(d, "_counter_collection.csv"):
+            k = r["Kernel_Name"]
+            per.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    return {k: {c: statistics.mean(v) for c, v in cs.items()} for k, cs in per.items()}
+
+
+def derived(c, n_cu=256, n_xcd=8):
+    """Ratios of one kernel's counters (None where a counter is missing).
+    GRBM_GUI_ACTIVE is summed over the XCDs, so the dispatch's duration in
+    cycles is GRBM_GUI_ACTIVE / n_xcd, and its CU-cycles that times n_cu.
+      valu_util: SIMD issue time spent on VALU, SQ_ACTIVE_INST_VALU (quad-
+        cycles, one per wave64 VALU instruction) x 4 / (4 n_cu x cycles);
+      lds_util: CU time the LDS works on indexed operations
+        (SQ_LDS_IDX_ACTIVE / CU-cycles);
+      lds_bank_conflict, lds_addr_conflict: CU time the LDS stalls on bank
+        and address conflicts (SQ_LDS_BANK_CONFLICT, SQ_LDS_ADDR_CONFLICT
+        over CU-cycles);
+      lds_issue_wait: wave time spent waiting to issue an LDS instruction
+        (SQ_WAIT_INST_LDS / SQ_WAVE_CYCLES)."""
+    out = {}
+    if c.get("GRBM_GUI_ACTIVE"):
+        cyc = c["GRBM_GUI_ACTIVE"] / n_xcd
+        cu = cyc * n_cu
+        out["cycles"] = round(cyc)
+        if "SQ_ACTIVE_INST_VALU" in c:
+            out["valu_util"] = round(c["SQ_ACTIVE_INST_VALU"] * 4 / (4 * cu), 4)
+        for key, name in (("lds_util", "SQ_LDS_IDX_ACTIVE"), ("lds_bank_conflict", "SQ_LDS_BANK_CONFLICT"),
+                          ("lds_addr_conflict", "SQ_LDS_ADDR_CONFLICT")):
+            if name in c:
+                out[key] = round(c[name] / cu, 4)
+    if c.get("SQ_WAVE_CYCLES") and "SQ_WAIT_INST_LDS" in c:
+        out["lds_issue_wait"] = round(c["SQ_WAIT_INST_LDS"] / c["SQ_WAVE_CYCLES"], 4)
+    return out
+
+
+def write_workload_markdown(title, commands, trace_dir, fetch_dir, write_dir, copy_bytes, pmc_dirs,
+                            out, run_file=None, units=None):
+    """Summary of one workload: trace, calibrated FETCH/WRITE bytes and SQ
+    counters per kernel.  units: {kernel substring: (count, what)} to print
+    counters per work unit (e.g. per 16 KiB tile)."""
+    if not copy_bytes and run_file and os.path.exists(run_file):
+        with open(run_file) as f:
+            js = [ln for ln in f if ln.strip().startswith("{")]
+        copy_bytes = json.loads(js[-1])["copy"]["bytes"]
+    s = summarize(trace_dir, fetch_dir, write_dir, None, copy_bytes, commands)
+    sq = counter_passes(pmc_dirs) if pmc_dirs else {}
+    for name, k in s["kernels"].items():
+        if name in sq:
+            k["counters"] = {c: round(v, 1) for c, v in sorted(sq[name].items())}
+            k["derived"] = derived(sq[name])
+            for sub, (n, what) in (units or {}).items():
+                if sub in name and n:
+                    k["per_" + what] = {c: round(sq[name][c] / n, 2) for c in
+                                        ("SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_SALU", "SQ_WAVES")
+                                        if c in sq[name]}
+    lines = ["# rocprofv3 summary: " + title, "", "Commands (run from the repository root on one MI355X):", ""]
+    lines += ["    " + c for c in commands]
+    cal = s["calibration"]
+    lines += ["", f"Counter calibration on `{cal['copy_kernel']}` ({cal['copy_bytes']} bytes read and "
+                  f"written): FETCH_SIZE x {cal['fetch_factor']}, WRITE_SIZE x {cal['write_factor']}.", "",
+              "| kernel | calls | mean us (trace) | HBM bytes/launch | VALU util | LDS util | "
+              "LDS bank-conflict | LDS addr-conflict | LDS issue wait |",
+              "|---|---|---|---|---|---|---|---|---|"]
+    for name, k in s["kernels"].items():
+        t = k["trace"] or {}
+        dv = k.get("derived", {})
+        short = name.replace("(anonymous namespace)::", "").split("(rfi::")[0]
+        lines.append(f"| `{short}` | {t.get('calls', '-')} | {t.get('avg_ns', 0) / 1e3:.1f} | "
+                     f"{k['hbm_bytes_per_launch']} | {dv.get('valu_util', '-')} | {dv.get('lds_util', '-')} | "
+                     f"{dv.get('lds_bank_conflict', '-')} | {dv.get('lds_addr_conflict', '-')} | "
+                     f"{dv.get('lds_issue_wait', '-')} |")
+    lines += ["", "Dispatch cycles = GRBM_GUI_ACTIVE / 8 (the counter is summed over the 8 XCDs). "
+                  "VALU util: SIMD issue time on VALU (SQ_ACTIVE_INST_VALU x 4 over 1024 SIMDs x cycles); "
+                  "LDS util, bank- and address-conflict: CU time the LDS works on indexed operations or "
+                  "stalls on conflicts (SQ_LDS_IDX_ACTIVE, SQ_LDS_BANK_CONFLICT, SQ_LDS_ADDR_CONFLICT over "
+                  "256 CUs x cycles); LDS issue wait: wave time waiting to issue an LDS instruction "
+                  "(SQ_WAIT_INST_LDS over SQ_WAVE_CYCLES).  Per-tile instruction counts are wave "
+                  "instructions summed over the tile's waves."]
+    if run_file and os.path.exists(run_file):
+        with open(run_file) as f:
+            js = [ln for ln in f if ln.strip().startswith("{")]
+        if js:
+            lines += ["", "Line printed by the traced run (HIP-event medians):", "", "    " + js[-1].strip()]
+    lines += ["", "```json", json.dumps({k: s[k] for k in ("kernel_source_sha256", "calibration", "kernels")},
+                                        indent=1), "```"]
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def load_summary(path):
     """The JSON block of a summary written by write_markdown."""
     text = open(path).read()
@@ -194,7 +287,20 @@ def main():
     ap.add_argument("--command", action="append", default=[])
     ap.add_argument("--trace-only", action="store_true")
     ap.add_argument("--title", default="")
+    ap.add_argument("--pmc", action="append", default=[], help="directory of an extra counter pass")
+    ap.add_argument("--units", action="append", default=[],
+                    help="KERNEL_SUBSTRING=COUNT:WHAT, counters per work unit")
     a = ap.parse_args()
+    if a.pmc:
+        units = {}
+        for u in a.units:
+            sub, rest = u.split("=", 1)
+            n, what = rest.split(":", 1)
+            units[sub] = (int(n), what)
+        write_workload_markdown(a.title, a.command, a.trace, a.fetch, a.write, a.copy_bytes, a.pmc, a.out,
+                                a.bench, units)
+        print(a.out)
+        return
     if a.trace_only:
         write_trace_markdown(a.trace, a.title, a.command, a.out, a.bench)
         print(a.out)
