@@ -665,7 +665,8 @@ def bench_serving(args, dev):
              "max_ms": round(float(lat_ms.max()), 4),
              "deadline_misses": int((lat > DEADLINE_NS).sum()),
              "gsamples_s": round(n_blocks * blen / wall / 1e9, 2),
-             "launches": c["launches"], "refused": c["refused"]}
+             "launches": c["launches"], "refused": c["refused"],
+             "ticket_records_live_peak": c["live_peak"], "ticket_records_live_at_end": c["live_records"]}
         return r
 
     def poisson(n):

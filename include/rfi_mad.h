@@ -296,7 +296,8 @@ int rfi_plan_info(const rfi_plan* plan, int32_t* n_launches, int64_t* n_windows,
                   int64_t* n_tiles, int64_t* n_generic);
 /* Time every schedule on the given buffers (iters executes each, median
  * per schedule), select the fastest and report it and its time (ms).
- * Writes y and stats. */
+ * Writes y and stats (as one execute would).  y must not be x
+ * (RFI_ERR_INVALID): the candidates run repeatedly on the same buffers. */
 int rfi_plan_autotune(rfi_plan* plan, const void* x, void* y, rfi_window_stats* stats_out,
                       void* stream, int32_t iters, int32_t* best_schedule, float* best_ms);
 int rfi_plan_destroy(rfi_plan* plan);
@@ -320,8 +321,24 @@ int rfi_shutdown(void);
 /* Output of a stream is emitted window by window: a submit emits the  */
 /* carry plus as many whole windows as the block completes, into       */
 /* out_dev, which must hold n + W - 1 elements.                        */
-/* Calls on one server are serialised by a mutex.  The server keeps a  */
-/* small record (about 80 bytes) per ticket until it is destroyed.     */
+/* Calls on one server are serialised by a mutex.                     */
+/* Ticket records: each admitted block has a record (about 100 bytes)  */
+/* until it is retired: a completed ticket once it has been polled     */
+/* done (at the next admission after that poll), a completed ticket   */
+/* never polled once 65536 later tickets have completed, and the       */
+/* tickets of rfi_server_replay as soon as they complete.  At most     */
+/* max_inflight + 65536 records are live; a poll-driven loop that      */
+/* polls its tickets as they complete keeps about max_inflight.        */
+/* Failures: if the work tables of a batch cannot be staged (memory),  */
+/* the batch is undone and its blocks wait for the next dispatch (the  */
+/* error is returned by dispatch, poll, sync; submit still admits).    */
+/* If a kernel launch or a completion query fails, the device state    */
+/* of the streams is unknown: the server is faulted and every later    */
+/* call except counters and destroy returns RFI_ERR_HIP.               */
+/* Testing aid: with the environment variable                          */
+/* RFI_SERVE_FAIL_UPLOAD=first[:count] set when a server is created,   */
+/* its table uploads number first .. first + count - 1 (counted from   */
+/* 1) fail with RFI_ERR_NOMEM, to exercise the undo.                   */
 /* ------------------------------------------------------------------ */
 typedef struct rfi_server rfi_server;
 
@@ -354,7 +371,9 @@ int rfi_server_submit(rfi_server* srv, uint32_t stream_id, const void* block_dev
  * launch per max_batch blocks).  Called by submit when a batch fills. */
 int rfi_server_dispatch(rfi_server* srv);
 /* done = 1 once the ticket's block has been filtered; samples_emitted and
- * windows_emitted report what its out/stats buffers received. */
+ * windows_emitted report what its out/stats buffers received.  A retired
+ * ticket (see above) reports done = 1 and -1 for both counts; a ticket id
+ * never issued is RFI_ERR_INVALID. */
 int rfi_server_poll(rfi_server* srv, uint64_t ticket, int32_t* done, int64_t* samples_emitted,
                     int64_t* windows_emitted);
 /* Block until every admitted block has completed. */
@@ -370,11 +389,13 @@ int rfi_server_snapshot(rfi_server* srv, uint32_t stream_id, int64_t* next_index
                         int32_t* carry_len, void* carry_host);
 int rfi_server_restore(rfi_server* srv, uint32_t stream_id, int64_t next_index,
                        int32_t carry_len, const void* carry_host);
-/* Counters: admitted, refused (BUSY), completed, launches. */
-int rfi_server_counters(const rfi_server* srv, uint64_t* admitted, uint64_t* refused,
-                        uint64_t* completed, uint64_t* launches);
+/* Counters: admitted, refused (BUSY), completed, launches, ticket
+ * records live now and at most so far (any pointer may be NULL). */
+int rfi_server_counters(rfi_server* srv, uint64_t* admitted, uint64_t* refused, uint64_t* completed,
+                        uint64_t* launches, uint64_t* live_records, uint64_t* live_peak);
 /* Host steady-clock times (ns) of a ticket's admission and of the moment
- * the server saw its batch complete (0 while not complete). */
+ * the server saw its batch complete (0 while not complete; -1 for both
+ * once the ticket is retired). */
 int rfi_server_ticket_times(rfi_server* srv, uint64_t ticket, int64_t* t_submit_ns,
                             int64_t* t_done_ns);
 /* Real-time replay: block i of stream stream_ids[i] (device buffers

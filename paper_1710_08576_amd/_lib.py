@@ -81,7 +81,7 @@ _SIGS = {
     "rfi_server_flush": (ctypes.c_int, [P, U32, P, P, P]),
     "rfi_server_snapshot": (ctypes.c_int, [P, U32, P, P, P]),
     "rfi_server_restore": (ctypes.c_int, [P, U32, I64, I32, P]),
-    "rfi_server_counters": (ctypes.c_int, [P, P, P, P, P]),
+    "rfi_server_counters": (ctypes.c_int, [P, P, P, P, P, P, P]),
     "rfi_server_ticket_times": (ctypes.c_int, [P, U64, P, P]),
     "rfi_server_replay": (ctypes.c_int, [P, I64, P, P, P, P, P, P, P, P]),
     "rfi_server_destroy": (ctypes.c_int, [P]),
@@ -448,10 +448,11 @@ class Server:
                                          _ptr(c) if len(c) else None), "rfi_server_restore")
 
     def counters(self):
-        v = [ctypes.c_uint64() for _ in range(4)]
+        v = [ctypes.c_uint64() for _ in range(6)]
         _check(load().rfi_server_counters(self.h, *[ctypes.byref(x) for x in v]),
                "rfi_server_counters")
-        return dict(zip(("admitted", "refused", "completed", "launches"), (x.value for x in v)))
+        return dict(zip(("admitted", "refused", "completed", "launches", "live_records", "live_peak"),
+                        (x.value for x in v)))
 
     def ticket_times(self, ticket):
         a, b = ctypes.c_int64(), ctypes.c_int64()

@@ -655,6 +655,9 @@ int rfi_plan_autotune(rfi_plan* plan, const void* x, void* y, rfi_window_stats* 
     int rc = rfi_validate(plan->elem, x, y, plan->n, plan->L.data(), plan->W.data(), plan->K.data(),
                           plan->M.data(), stats_out);
     if (rc != RFI_OK) return rc;
+    // Every candidate runs several times on these buffers: in place, each
+    // run would filter the output of the one before.
+    if (x == y && plan->n_windows > 0) return RFI_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return hip_fail(hipGetLastError());

@@ -19,13 +19,28 @@
 // different lanes, and of queued batches, overlaps on the device.  Blocks
 // are admitted against an HBM budget (input + output + statistics bytes of
 // unfinished blocks) and an in-flight limit.
+//
+// Ticket records live in a map keyed by ticket id and are retired: a
+// completed record once it has been polled done (at the next admission), a
+// completed record never polled once kTicketHistory later tickets have
+// completed, and a replay's records as soon as their results are taken.
+// Memory thus stays bounded over an unbounded run.
+//
+// A batch is built on the host before anything reaches the device; if its
+// tables cannot be staged or copied, the stream state it changed (carry
+// position and length, absolute index, pending queue, ticket states) is
+// restored and its blocks wait for the next dispatch.  A failed kernel
+// launch or completion query leaves device state unknown: the server is
+// then faulted and every later call returns RFI_ERR_HIP.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <mutex>
+#include <unordered_map>
 #include <vector>
 
 #include "rfi_runtime.hpp"
@@ -60,7 +75,11 @@ struct SrvStream {
 
 enum TicketState { kAdmitted = 0, kDispatched = 1, kDone = 2 };
 
+// Completed, never-polled records kept before the oldest is retired.
+constexpr size_t kTicketHistory = 65536;
+
 struct TicketRec {
+    bool polled = false;
     uint32_t stream = 0;
     const void* block = nullptr;
     void* out = nullptr;
@@ -98,6 +117,12 @@ struct Chain {
 
 constexpr size_t kSlotPrealloc = 1 << 20;  // table bytes per slot at creation
 
+struct SavedState {
+    int cur;
+    int32_t carry_len;
+    int64_t next_abs;
+};
+
 struct Lane {
     hipStream_t s = nullptr;
     Slot slots[kSlotsPerLane];
@@ -110,6 +135,7 @@ struct Lane {
     std::vector<CarryItem> carries;
     std::vector<uint64_t> batch;
     std::vector<Chain> chains;
+    std::vector<SavedState> saved;  // members' state before the batch
 };
 
 }  // namespace
@@ -118,13 +144,27 @@ struct rfi_server {
     rfi_server_config cfg;
     int device = 0;
     std::vector<SrvStream> streams;
-    std::deque<TicketRec> tickets;  // index = ticket id - 1 (never relocated)
+    std::unordered_map<uint64_t, TicketRec> recs;  // live ticket records by id
+    uint64_t next_id = 1;                          // ids 1 .. next_id - 1 issued
+    std::deque<uint64_t> completed;                // completion order (history bound)
+    std::vector<uint64_t> polled;                  // polled done, retired at the next admission
+    uint64_t live_peak = 0;
+    // Replay in progress: results of its tickets [first, first + n) are
+    // written here at completion and the records retired at once.
+    uint64_t sink_first = 0;
+    int64_t sink_n = 0;
+    int64_t* sink_done = nullptr;
+    int64_t* sink_emitted = nullptr;
     std::vector<Lane> lanes;
     uint64_t bytes_inflight = 0;
     int64_t inflight = 0;
     uint64_t n_admitted = 0, n_refused = 0, n_completed = 0, n_launches = 0;
     int persist_grid = 0;
-    hipError_t fault = hipSuccess;  // first failed completion query
+    hipError_t fault = hipSuccess;  // first failed launch or completion query
+    // Testing aid: uploads number fail_from .. fail_from + fail_count - 1
+    // (counted from 1 per server) fail as if staging memory were exhausted
+    // (environment RFI_SERVE_FAIL_UPLOAD=first[:count], read at creation).
+    uint64_t uploads = 0, fail_from = 0, fail_count = 0;
     std::mutex mu;
 };
 
@@ -300,16 +340,19 @@ int dispatch_lane(rfi_server* srv, int li)
             break;
         }
     if (si < 0 || L.members.empty()) return RFI_OK;
+    if (srv->fault != hipSuccess) return hip_fail(srv->fault);
     L.descs.clear();
     L.items.clear();
     L.carries.clear();
     L.batch.clear();
     const int nm = (int)L.members.size();
     L.chains.assign(nm, Chain());
+    L.saved.resize(nm);
     for (int j = 0; j < nm; ++j) {
         const SrvStream& st = srv->streams[L.members[j]];
         L.chains[j].src = (uint64_t)(uintptr_t)st.carry[st.cur];
         L.chains[j].len = st.carry_len;
+        L.saved[j] = SavedState{st.cur, st.carry_len, st.next_abs};
     }
     // Round-robin passes: each pass takes the next block of every stream
     // whose chain is still open.
@@ -323,7 +366,7 @@ int dispatch_lane(rfi_server* srv, int li)
             if (st.pending.empty() || !L.chains[j].open) continue;
             const uint64_t tk = st.pending.front();
             st.pending.pop_front();
-            TicketRec& t = srv->tickets[tk - 1];
+            TicketRec& t = srv->recs.at(tk);
             plan_block(srv, st, sid, t, L.chains[j], L);
             t.state = kDispatched;
             L.batch.push_back(tk);
@@ -337,8 +380,26 @@ int dispatch_lane(rfi_server* srv, int li)
     StreamDesc* dd = nullptr;
     Item* di = nullptr;
     CarryItem* dc = nullptr;
-    int rc = upload(sl, L.descs, L.items, L.carries, L.s, &dd, &di, &dc);
-    if (rc != RFI_OK) return rc;
+    int rc = RFI_OK;
+    if (++srv->uploads >= srv->fail_from && srv->uploads < srv->fail_from + srv->fail_count) rc = RFI_ERR_NOMEM;
+    if (rc == RFI_OK) rc = upload(sl, L.descs, L.items, L.carries, L.s, &dd, &di, &dc);
+    if (rc != RFI_OK) {
+        // Nothing of this batch reached the device: undo it.
+        for (int j = 0; j < nm; ++j) {
+            SrvStream& st = srv->streams[L.members[j]];
+            st.cur = L.saved[j].cur;
+            st.carry_len = L.saved[j].carry_len;
+            st.next_abs = L.saved[j].next_abs;
+        }
+        for (auto it = L.batch.rbegin(); it != L.batch.rend(); ++it) {
+            TicketRec& t = srv->recs.at(*it);
+            t.state = kAdmitted;
+            t.emitted_samples = t.emitted_windows = 0;
+            srv->streams[t.stream].pending.push_front(*it);
+        }
+        L.rr = (L.rr + nm - 1) % nm;
+        return rc;
+    }
     hipError_t e = hipSuccess;
     const std::vector<Item>& items = L.items;
     const std::vector<CarryItem>& carries = L.carries;
@@ -361,7 +422,12 @@ int dispatch_lane(rfi_server* srv, int li)
         ++srv->n_launches;
     }
     if (e == hipSuccess) e = hipEventRecord(sl.ev, L.s);
-    if (e != hipSuccess) return hip_fail(e);
+    if (e != hipSuccess) {
+        // Part of the batch may be on the device: the server cannot tell
+        // what its streams' carries hold any more.
+        srv->fault = e;
+        return hip_fail(e);
+    }
     sl.busy = true;
     sl.tickets.assign(L.batch.begin(), L.batch.end());
     L.inflight.push_back(si);
@@ -384,7 +450,8 @@ int64_t reap(rfi_server* srv, uint64_t min_id = 0, int64_t* ours = nullptr)
             }
             const int64_t t = now_ns();
             for (uint64_t tk : sl.tickets) {
-                TicketRec& r = srv->tickets[tk - 1];
+                auto it = srv->recs.find(tk);
+                TicketRec& r = it->second;
                 r.state = kDone;
                 r.t_done = t;
                 srv->bytes_inflight -= r.bytes;
@@ -392,6 +459,17 @@ int64_t reap(rfi_server* srv, uint64_t min_id = 0, int64_t* ours = nullptr)
                 ++srv->n_completed;
                 ++done;
                 if (ours && tk >= min_id) ++*ours;
+                if (srv->sink_n > 0 && tk >= srv->sink_first && tk < srv->sink_first + (uint64_t)srv->sink_n) {
+                    srv->sink_done[tk - srv->sink_first] = t;
+                    srv->sink_emitted[tk - srv->sink_first] = r.emitted_samples;
+                    srv->recs.erase(it);
+                    continue;
+                }
+                srv->completed.push_back(tk);
+                if (srv->completed.size() > kTicketHistory) {
+                    srv->recs.erase(srv->completed.front());
+                    srv->completed.pop_front();
+                }
             }
             sl.tickets.clear();
             sl.busy = false;
@@ -407,8 +485,11 @@ int submit_locked(rfi_server* srv, uint32_t sid, const void* block, void* out, i
     if (sid >= (uint32_t)srv->streams.size() || !srv->streams[sid].active || n < 0) return RFI_ERR_INVALID;
     if (n > 0 && (!block || !out)) return RFI_ERR_INVALID;
     if (((uintptr_t)block | (uintptr_t)out | (uintptr_t)stats) & 15u) return RFI_ERR_ALIGN;
+    if (srv->fault != hipSuccess) return hip_fail(srv->fault);
     SrvStream& st = srv->streams[sid];
     const uint64_t bytes = block_bytes(srv, st, n);
+    for (uint64_t id : srv->polled) srv->recs.erase(id);
+    srv->polled.clear();
     if (srv->inflight >= srv->cfg.max_inflight ||
         (srv->bytes_inflight + bytes > srv->cfg.hbm_budget_bytes && srv->inflight > 0)) {
         ++srv->n_refused;
@@ -422,8 +503,9 @@ int submit_locked(rfi_server* srv, uint32_t sid, const void* block, void* out, i
     t.stats = stats;
     t.bytes = bytes;
     t.t_submit = now_ns();
-    srv->tickets.push_back(t);
-    const uint64_t id = srv->tickets.size();
+    const uint64_t id = srv->next_id++;
+    srv->recs.emplace(id, t);
+    srv->live_peak = std::max<uint64_t>(srv->live_peak, srv->recs.size());
     st.pending.push_back(id);
     srv->bytes_inflight += bytes;
     ++srv->inflight;
@@ -445,6 +527,7 @@ int dispatch_all(rfi_server* srv)
 int sync_all(rfi_server* srv)
 {
     for (;;) {
+        if (srv->fault != hipSuccess) return hip_fail(srv->fault);
         reap(srv);
         if (srv->fault != hipSuccess) return hip_fail(srv->fault);
         int rc = dispatch_all(srv);
@@ -474,6 +557,16 @@ int rfi_server_create(const rfi_server_config* cfg, rfi_server** out)
     srv->cfg = *cfg;
     if (hipGetDevice(&srv->device) != hipSuccess) srv->device = 0;
     srv->persist_grid = persistent_grid(cfg->elem_size, -1, 7, true);
+    if (const char* f = std::getenv("RFI_SERVE_FAIL_UPLOAD")) {
+        char* end = nullptr;
+        const unsigned long long first = std::strtoull(f, &end, 10);
+        unsigned long long count = 1;
+        if (end && *end == ':') count = std::strtoull(end + 1, nullptr, 10);
+        if (first > 0) {
+            srv->fail_from = first;
+            srv->fail_count = count;
+        }
+    }
     srv->streams.resize(cfg->max_streams);
     srv->lanes.resize(cfg->n_lanes);
     for (auto& L : srv->lanes) {
@@ -525,14 +618,19 @@ int rfi_server_submit(rfi_server* srv, uint32_t stream_id, const void* block_dev
     std::lock_guard<std::mutex> g(srv->mu);
     int rc = submit_locked(srv, stream_id, block_dev, out_dev, n, stats_dev, ticket);
     if (rc != RFI_OK) return rc;
-    return dispatch_lane(srv, srv->streams[stream_id].lane);
+    // The block is admitted: a batch that could not be staged stays queued
+    // for the next dispatch; only a fault is reported here.
+    rc = dispatch_lane(srv, srv->streams[stream_id].lane);
+    return srv->fault != hipSuccess ? rc : RFI_OK;
 }
 
 int rfi_server_dispatch(rfi_server* srv)
 {
     if (!srv) return RFI_ERR_INVALID;
     std::lock_guard<std::mutex> g(srv->mu);
+    if (srv->fault != hipSuccess) return hip_fail(srv->fault);
     reap(srv);
+    if (srv->fault != hipSuccess) return hip_fail(srv->fault);
     return dispatch_all(srv);
 }
 
@@ -541,13 +639,25 @@ int rfi_server_poll(rfi_server* srv, uint64_t ticket, int32_t* done, int64_t* sa
 {
     if (!srv || ticket == 0) return RFI_ERR_INVALID;
     std::lock_guard<std::mutex> g(srv->mu);
-    if (ticket > srv->tickets.size()) return RFI_ERR_INVALID;
+    if (ticket >= srv->next_id) return RFI_ERR_INVALID;
+    if (srv->fault != hipSuccess) return hip_fail(srv->fault);
     reap(srv);
-    int rc = dispatch_all(srv);
-    const TicketRec& t = srv->tickets[ticket - 1];
+    int rc = srv->fault != hipSuccess ? hip_fail(srv->fault) : dispatch_all(srv);
+    auto it = srv->recs.find(ticket);
+    if (it == srv->recs.end()) {  // retired: it completed earlier
+        if (done) *done = 1;
+        if (samples_emitted) *samples_emitted = -1;
+        if (windows_emitted) *windows_emitted = -1;
+        return rc;
+    }
+    TicketRec& t = it->second;
     if (done) *done = t.state == kDone ? 1 : 0;
     if (samples_emitted) *samples_emitted = t.state >= kDispatched ? t.emitted_samples : 0;
     if (windows_emitted) *windows_emitted = t.state >= kDispatched ? t.emitted_windows : 0;
+    if (t.state == kDone && !t.polled) {
+        t.polled = true;
+        srv->polled.push_back(ticket);
+    }
     return rc;
 }
 
@@ -649,14 +759,17 @@ int rfi_server_restore(rfi_server* srv, uint32_t stream_id, int64_t next_index, 
     return RFI_OK;
 }
 
-int rfi_server_counters(const rfi_server* srv, uint64_t* admitted, uint64_t* refused,
-                        uint64_t* completed, uint64_t* launches)
+int rfi_server_counters(rfi_server* srv, uint64_t* admitted, uint64_t* refused, uint64_t* completed,
+                        uint64_t* launches, uint64_t* live_records, uint64_t* live_peak)
 {
     if (!srv) return RFI_ERR_INVALID;
+    std::lock_guard<std::mutex> g(srv->mu);
     if (admitted) *admitted = srv->n_admitted;
     if (refused) *refused = srv->n_refused;
     if (completed) *completed = srv->n_completed;
     if (launches) *launches = srv->n_launches;
+    if (live_records) *live_records = srv->recs.size();
+    if (live_peak) *live_peak = srv->live_peak;
     return RFI_OK;
 }
 
@@ -664,8 +777,14 @@ int rfi_server_ticket_times(rfi_server* srv, uint64_t ticket, int64_t* t_submit_
 {
     if (!srv || ticket == 0) return RFI_ERR_INVALID;
     std::lock_guard<std::mutex> g(srv->mu);
-    if (ticket > srv->tickets.size()) return RFI_ERR_INVALID;
-    const TicketRec& t = srv->tickets[ticket - 1];
+    if (ticket >= srv->next_id) return RFI_ERR_INVALID;
+    auto it = srv->recs.find(ticket);
+    if (it == srv->recs.end()) {  // retired
+        if (t_submit_ns) *t_submit_ns = -1;
+        if (t_done_ns) *t_done_ns = -1;
+        return RFI_OK;
+    }
+    const TicketRec& t = it->second;
     if (t_submit_ns) *t_submit_ns = t.t_submit;
     if (t_done_ns) *t_done_ns = t.state == kDone ? t.t_done : 0;
     return RFI_OK;
@@ -682,36 +801,52 @@ int rfi_server_replay(rfi_server* srv, int64_t n_blocks, const uint32_t* stream_
     for (int64_t i = 1; i < n_blocks; ++i)
         if (arrival_ns[i] < arrival_ns[i - 1]) return RFI_ERR_INVALID;
     std::lock_guard<std::mutex> g(srv->mu);
-    std::vector<uint64_t> tk(n_blocks, 0);
+    if (srv->fault != hipSuccess) return hip_fail(srv->fault);
+    std::vector<int64_t> done_at(n_blocks, 0), emitted(n_blocks, 0);
     std::deque<int64_t> waiting;  // arrived, not yet admitted (arrival order)
     // The lock is held throughout, so this call's tickets are numbered
-    // consecutively from first_id in arrival order.
-    const uint64_t first_id = srv->tickets.size() + 1;
+    // consecutively from first_id in arrival order; their results are taken
+    // at completion (sink) and their records retired at once.
+    const uint64_t first_id = srv->next_id;
+    srv->sink_first = first_id;
+    srv->sink_n = n_blocks;
+    srv->sink_done = done_at.data();
+    srv->sink_emitted = emitted.data();
     int64_t next = 0, finished = 0;
+    int rc = RFI_OK;
     const int64_t t0 = now_ns();
     while (finished < n_blocks) {
         const int64_t now = now_ns() - t0;
         while (next < n_blocks && arrival_ns[next] <= now) waiting.push_back(next++);
         while (!waiting.empty()) {
             const int64_t i = waiting.front();
-            const int rc = submit_locked(srv, stream_ids[i], blocks[i], outs[i], lengths[i],
-                                         stats ? stats[i] : nullptr, &tk[i]);
-            if (rc == RFI_ERR_BUSY) break;
-            if (rc != RFI_OK) {
-                (void)sync_all(srv);
-                return rc;
+            uint64_t id = 0;
+            rc = submit_locked(srv, stream_ids[i], blocks[i], outs[i], lengths[i], stats ? stats[i] : nullptr, &id);
+            if (rc == RFI_ERR_BUSY) {
+                rc = RFI_OK;
+                break;
             }
+            if (rc != RFI_OK) break;
             waiting.pop_front();
         }
-        const int rc = dispatch_all(srv);
-        if (rc != RFI_OK) return rc;
+        if (rc != RFI_OK) {
+            (void)sync_all(srv);
+            break;
+        }
+        rc = dispatch_all(srv);
+        if (rc != RFI_OK) break;
         reap(srv, first_id, &finished);
-        if (srv->fault != hipSuccess) return hip_fail(srv->fault);
+        if (srv->fault != hipSuccess) {
+            rc = hip_fail(srv->fault);
+            break;
+        }
     }
+    srv->sink_n = 0;
+    srv->sink_done = srv->sink_emitted = nullptr;
+    if (rc != RFI_OK) return rc;
     for (int64_t i = 0; i < n_blocks; ++i) {
-        const TicketRec& t = srv->tickets[tk[i] - 1];
-        latency_ns[i] = t.t_done - (t0 + arrival_ns[i]);
-        if (samples_emitted) samples_emitted[i] = t.emitted_samples;
+        latency_ns[i] = done_at[i] - (t0 + arrival_ns[i]);
+        if (samples_emitted) samples_emitted[i] = emitted[i];
     }
     return RFI_OK;
 }

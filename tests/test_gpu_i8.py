@@ -238,6 +238,22 @@ def test_autotune_picks_a_schedule_and_keeps_the_bytes(gpu):
     q.close()
 
 
+def test_autotune_rejects_in_place(gpu):
+    """Autotuning runs every candidate repeatedly on the caller's buffers, so
+    an in-place call (y == x) is refused and leaves x untouched."""
+    specs = synth.batching(n_streams=4, lo=1 << 14, hi=1 << 15, seed=9)
+    x = synth.gen_packed(specs, seed=9, tag=9)
+    L, W, K, M = unpack(specs)
+    xd = x.to(gpu)
+    p = rfi.Plan(1, L, W, K, M, seed=5)
+    with pytest.raises(rfi.RfiError) as e:
+        p.autotune(xd, xd, None, iters=1)
+    assert e.value.status == -1
+    torch.cuda.synchronize()
+    assert torch.equal(xd.cpu(), x)
+    p.close()
+
+
 # 4066 / 4067 and 8162 / 8163: the longest windows of the 64- and 128-thread
 # generic workgroups and the first past them; 4081 / 4082 and 8177 / 8178:
 # the most chunks those workgroups can hold at some phase

@@ -490,3 +490,161 @@ def test_burst_batches_chain_carries(gpu, max_batch):
         assert_same(np.concatenate(ys[i] + [fy]), np.concatenate(sts[i] + [fs]), yo[i], sto[i],
                     f"burst stream {i} W={specs[i].window}")
     srv.close()
+
+
+def _served_streams(specs, xs, ev_blocks, outs_host, stride, em):
+    """Per-stream concatenated outputs of blocks replayed into one output
+    buffer per stream at a fixed stride (ev_blocks: (stream, slot) in
+    arrival order)."""
+    ys = {i: [] for i in range(len(specs))}
+    for (i, slot), e in zip(ev_blocks, em):
+        ys[i].append(outs_host[i][slot * stride:slot * stride + e])
+    return ys
+
+
+@pytest.mark.gpu
+def test_ticket_records_bounded_over_1e5_replayed_blocks(gpu):
+    """10^5 blocks replayed (every block ready at once, so admission runs at
+    its limit throughout): the ticket records retire as blocks complete, so
+    the live count never exceeds the in-flight limit and ends at zero, and
+    every stream's output equals the oracle's."""
+    specs = [synth.StreamSpec(0, W, 3.0, m, 10.0, 0.01, 8, 200)
+             for W, m in [(1024, 1), (4096, 2), (2048, 0), (3000, 2)]]
+    nblk, n = 25_000, 2048
+    for s in specs:
+        s.length = nblk * n
+    xs = make_streams(specs, SEED + 6)
+    yo, _ = oracle_streams(xs, specs, SEED + 6)
+    max_inflight = 64
+    srv = rfi.Server(elem_size=1, max_streams=len(specs), max_inflight=max_inflight, max_batch=16,
+                     hbm_budget_bytes=1 << 32, seed=SEED + 6, n_lanes=2)
+    for i, s in enumerate(specs):
+        srv.add_stream(i, s.window, s.k, s.mode)
+    xd = [torch.from_numpy(x).to(gpu) for x in xs]
+    stride = (n + 4096 - 1 + 15) // 16 * 16
+    outs = [torch.full((nblk * stride,), 0x5A, dtype=torch.int8, device=gpu) for _ in specs]
+    sid = np.tile(np.arange(len(specs), dtype=np.uint32), nblk)
+    slot = np.repeat(np.arange(nblk, dtype=np.int64), len(specs))
+    bp = np.array([xd[i].data_ptr() for i in range(len(specs))], dtype=np.uint64)[sid] + \
+        (slot * n).astype(np.uint64)
+    op = np.array([o.data_ptr() for o in outs], dtype=np.uint64)[sid] + (slot * stride).astype(np.uint64)
+    assert len(sid) == 100_000
+    lat, em = srv.replay_ptrs(sid, np.zeros(len(sid), np.int64), bp, op, np.full(len(sid), n, np.int64))
+    c = srv.counters()
+    assert c["completed"] == len(sid)
+    assert c["live_records"] == 0
+    assert c["live_peak"] <= max_inflight
+    assert np.all(lat > 0)
+    outs_host = [o.cpu().numpy() for o in outs]
+    ys = _served_streams(specs, xs, zip(sid.tolist(), slot.tolist()), outs_host, stride, em)
+    drv = Served(srv, gpu, specs, torch.int8)
+    for i in range(len(specs)):
+        drv.flush(i)
+        fy, _ = drv.result(i)
+        y = np.concatenate(ys[i] + [fy])
+        assert len(y) == len(yo[i]) and np.array_equal(y, yo[i]), f"stream {i}"
+    srv.close()
+
+
+@pytest.mark.gpu
+def test_ticket_records_bounded_poll_loop(gpu):
+    """A submit/poll loop (2 x 10^4 blocks; the client keeps at most
+    max_inflight tickets outstanding and polls the oldest to completion
+    before submitting more): polled records retire, so the live count
+    stays within the in-flight limit; retired tickets report done with
+    unknown counts; the output equals the oracle's."""
+    specs = [synth.StreamSpec(0, W, 3.0, m, 12.0, 0.01, 8, 200) for W, m in [(4096, 1), (1000, 2)]]
+    nblk, n = 10_000, 3008
+    for s in specs:
+        s.length = nblk * n
+    xs = make_streams(specs, SEED + 7)
+    yo, _ = oracle_streams(xs, specs, SEED + 7)
+    max_inflight = 32
+    srv = rfi.Server(elem_size=1, max_streams=2, max_inflight=max_inflight, max_batch=8,
+                     hbm_budget_bytes=1 << 32, seed=SEED + 7, n_lanes=1)
+    for i, s in enumerate(specs):
+        srv.add_stream(i, s.window, s.k, s.mode)
+    xd = [torch.from_numpy(x).to(gpu) for x in xs]
+    stride = (n + 4096 - 1 + 15) // 16 * 16
+    outs = [torch.full((nblk * stride,), 0x5A, dtype=torch.int8, device=gpu) for _ in specs]
+    queue, emitted, peak = [], {}, 0
+    first = None
+    for b in range(nblk):
+        for i in range(2):
+            blk = xd[i][b * n:(b + 1) * n]
+            out = outs[i][b * stride:(b + 1) * stride]
+            while True:
+                t = srv.try_submit(i, blk, out, None, n=n) if len(queue) < max_inflight else None
+                if t is not None:
+                    break
+                t0, i0, b0 = queue.pop(0)
+                while True:
+                    done, se, _ = srv.poll(t0)
+                    if done:
+                        break
+                emitted[(i0, b0)] = se
+            first = first or t
+            queue.append((t, i, b))
+            peak = max(peak, srv.counters()["live_records"])
+    srv.sync()
+    for t, i, b in queue:
+        done, se, _ = srv.poll(t)
+        assert done
+        emitted[(i, b)] = se
+    assert peak <= max_inflight
+    assert srv.counters()["live_peak"] <= max_inflight
+    # the first ticket was polled long ago: retired, done with unknown counts
+    assert srv.poll(first) == (True, -1, -1)
+    assert srv.ticket_times(first) == (-1, -1)
+    with pytest.raises(rfi.RfiError):
+        srv.poll(10 ** 9)
+    drv = Served(srv, gpu, specs, torch.int8)
+    for i in range(2):
+        oh = outs[i].cpu().numpy()
+        parts = [oh[b * stride:b * stride + emitted[(i, b)]] for b in range(nblk)]
+        drv.flush(i)
+        fy, _ = drv.result(i)
+        y = np.concatenate(parts + [fy])
+        assert len(y) == len(yo[i]) and np.array_equal(y, yo[i]), f"stream {i}"
+    srv.close()
+
+
+@pytest.mark.gpu
+def test_failed_table_upload_is_undone(gpu, monkeypatch):
+    """Table uploads 3 and 4 fail (the server's testing hook): the batch
+    built for the third block is undone, its block stays queued, dispatch
+    reports the failure, and the next dispatch runs it from the restored
+    carry: every output equals the oracle's."""
+    specs = [synth.StreamSpec(0, W, 3.0, m, 10.0, 0.01, 8, 200) for W, m in [(4096, 2), (1000, 1)]]
+    sizes = [5000, 7000, 3001, 9000, 4096, 1]
+    for s in specs:
+        s.length = sum(sizes)
+    xs = make_streams(specs, SEED + 8)
+    yo, sto = oracle_streams(xs, specs, SEED + 8)
+    monkeypatch.setenv("RFI_SERVE_FAIL_UPLOAD", "3:2")
+    srv = rfi.Server(elem_size=1, max_streams=2, max_inflight=64, max_batch=64,
+                     hbm_budget_bytes=1 << 32, seed=SEED + 8, n_lanes=1)
+    monkeypatch.delenv("RFI_SERVE_FAIL_UPLOAD")
+    for i, s in enumerate(specs):
+        srv.add_stream(i, s.window, s.k, s.mode)
+    drv = Served(srv, gpu, specs, torch.int8)
+    pos = 0
+    for j, n in enumerate(sizes):
+        for i in range(2):
+            t = drv.submit(i, xs[i][pos:pos + n])
+            if j == 1 and i == 0:
+                # uploads so far: block 0 of each stream (1, 2, each synced);
+                # this block's batch is the third: undone, the block queued
+                with pytest.raises(rfi.RfiError) as e:
+                    srv.dispatch()  # the fourth upload fails too
+                assert e.value.status == -4
+                assert srv.counters()["completed"] == 2
+                srv.poll(t)  # the fifth succeeds
+            srv.sync()
+        pos += n
+    drv.collect()
+    for i in range(2):
+        drv.flush(i)
+        y, st = drv.result(i)
+        assert_same(y, st, yo[i], sto[i], f"stream {i}")
+    srv.close()
