@@ -265,7 +265,10 @@ typedef enum {
                                     stream                                 */
     RFI_SCHED_FUSED_CONCURRENT = 7, /* FUSED's per-mode launches on parallel
                                     streams, joined likewise             */
-    RFI_SCHED_COUNT = 8
+    RFI_SCHED_ONE_LAUNCH = 8,  /* the whole batch, every class and mode, as
+                                  one launch, one WG per item              */
+    RFI_SCHED_ONE_LAUNCH_PERSIST = 9, /* the same as one persistent launch */
+    RFI_SCHED_COUNT = 10
 } rfi_schedule;
 
 /* elem_size 1 or 2; arrays as in rfi_mad_filter.  Allocates device work
@@ -301,6 +304,25 @@ int rfi_plan_info(const rfi_plan* plan, int32_t* n_launches, int64_t* n_windows,
 int rfi_plan_autotune(rfi_plan* plan, const void* x, void* y, rfi_window_stats* stats_out,
                       void* stream, int32_t iters, int32_t* best_schedule, float* best_ms);
 int rfi_plan_destroy(rfi_plan* plan);
+
+/* Autotune table persistence.  The table maps (GPU architecture, plan
+ * signature: element size, window classes present, irregular windows,
+ * noise streams, generic work items) to the chosen schedule, tiles per
+ * workgroup and occupancy cap; RFI_SCHED_AUTO plans and the cached batch
+ * entry points use it.
+ * rfi_tune_save writes every entry of this process's table as JSON
+ * ({"entries": [{"arch", "signature" (hex), "schedule" (name), "tiles_per_wg",
+ * "wg_per_cu", "ms", and readable signature fields}]}), replacing `path`
+ * atomically (a temporary file renamed).  rfi_tune_load adds the entries of
+ * such a file (entries of other architectures are kept but match no
+ * device here), replacing those of equal keys; a plan built afterwards
+ * uses them.  Both are host only.  Errors: RFI_ERR_INVALID (NULL path,
+ * file not readable or writable, malformed file: nothing is loaded).
+ * With the environment variable RFI_TUNE_FILE set, the library loads that
+ * file when it builds its first plan (a missing file is no error) and
+ * writes the table to it after every rfi_plan_autotune. */
+int rfi_tune_save(const char* path);
+int rfi_tune_load(const char* path);
 
 /* Drop cached plans and graphs (all devices of this process). */
 int rfi_shutdown(void);

@@ -10,5 +10,5 @@ generator used by tests and benchmarks.
 """
 from ._lib import (  # noqa: F401
     CLIP, NOISE, ZERO, SCHEDULES, STATS_DTYPE, Plan, RfiError, Server, block_power, improvement, layout, load,
-    mad_filter, mad_filter_multi, mad_filter_noalloc, mom_filter, mom_filter_carry, n_blocks, stats_numpy, validate,
+    mad_filter, mad_filter_multi, mad_filter_noalloc, mom_filter, mom_filter_carry, n_blocks, stats_numpy, tune_load, tune_save, validate,
 )

@@ -22,9 +22,10 @@ STATUS = {0: "RFI_OK", -1: "RFI_ERR_INVALID", -2: "RFI_ERR_ALIGN", -3: "RFI_ERR_
           -4: "RFI_ERR_NOMEM", -5: "RFI_ERR_HIP", -6: "RFI_ERR_BUSY"}
 ZERO, CLIP, NOISE = 0, 1, 2
 (SCHED_AUTO, SCHED_SPLIT, SCHED_SPLIT_PERSIST, SCHED_FUSED, SCHED_PER_STREAM, SCHED_FUSED_PERSIST,
- SCHED_SPLIT_CONCURRENT, SCHED_FUSED_CONCURRENT) = range(8)
+ SCHED_SPLIT_CONCURRENT, SCHED_FUSED_CONCURRENT, SCHED_ONE_LAUNCH, SCHED_ONE_LAUNCH_PERSIST) = range(10)
 SCHEDULES = {"auto": 0, "split": 1, "split_persist": 2, "fused": 3, "per_stream": 4,
-             "fused_persist": 5, "split_concurrent": 6, "fused_concurrent": 7}
+             "fused_persist": 5, "split_concurrent": 6, "fused_concurrent": 7, "one_launch": 8,
+             "one_launch_persist": 9}
 
 STATS_DTYPE = np.dtype(
     [("median", "<i4"), ("mad", "<i4"), ("n_flagged", "<u4"), ("threshold", "<f4")]
@@ -72,6 +73,8 @@ _SIGS = {
     "rfi_plan_autotune": (ctypes.c_int, [P, P, P, P, P, I32, P, P]),
     "rfi_plan_destroy": (ctypes.c_int, [P]),
     "rfi_shutdown": (ctypes.c_int, []),
+    "rfi_tune_save": (ctypes.c_int, [ctypes.c_char_p]),
+    "rfi_tune_load": (ctypes.c_int, [ctypes.c_char_p]),
     "rfi_server_create": (ctypes.c_int, [P, PP]),
     "rfi_server_add_stream": (ctypes.c_int, [P, U32, I32, F32, I32]),
     "rfi_server_submit": (ctypes.c_int, [P, U32, P, P, I64, P, P]),
@@ -180,6 +183,16 @@ def ubench_lds_hist(x, replicas=4, hist=None, stream=None):
     _check(load().rfi_ubench_lds_hist(_tptr(x), nbytes, int(replicas), _tptr(hist), _stream_handle(stream)),
            "rfi_ubench_lds_hist")
     return hist
+
+
+def tune_save(path: str):
+    """Write the autotune table to a JSON file (rfi_tune_save)."""
+    _check(load().rfi_tune_save(os.fsencode(path)), "rfi_tune_save")
+
+
+def tune_load(path: str):
+    """Add the entries of a saved autotune table (rfi_tune_load)."""
+    _check(load().rfi_tune_load(os.fsencode(path)), "rfi_tune_load")
 
 
 def stats_numpy(stats_t) -> np.ndarray:

@@ -5,6 +5,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -45,59 +47,197 @@ int validate_values(int elem, int32_t n, const int64_t* L, const int32_t* W, con
 }
 
 // ---------------------------------------------------------------------------
-// Autotune table: schedule chosen for a coarse plan signature.
+// Autotune table: launch choice per (GPU architecture, coarse plan
+// signature), filled by rfi_plan_autotune, saved to and loaded from JSON.
 // ---------------------------------------------------------------------------
-static std::mutex g_tune_mu;
-static std::map<uint64_t, int> g_tune;
-
-uint64_t plan_signature(const rfi_plan* p);
-int tuned_tpw(uint64_t sig);
-
-int tuned_schedule(uint64_t sig)
-{
-    std::lock_guard<std::mutex> g(g_tune_mu);
-    auto it = g_tune.find(sig);
-    return it == g_tune.end() ? RFI_SCHED_SPLIT : it->second;
-}
-
-void record_schedule(uint64_t sig, int sched)
-{
-    std::lock_guard<std::mutex> g(g_tune_mu);
-    g_tune[sig] = sched;
-}
-
-static std::map<uint64_t, int> g_tune_tpw;
-
-int tuned_tpw(uint64_t sig)
-{
-    std::lock_guard<std::mutex> g(g_tune_mu);
-    auto it = g_tune_tpw.find(sig);
-    return it == g_tune_tpw.end() ? 1 : it->second;
-}
-
-void record_tpw(uint64_t sig, int tpw)
-{
-    std::lock_guard<std::mutex> g(g_tune_mu);
-    g_tune_tpw[sig] = tpw;
-}
+struct TuneEntry {
+    int sched;
+    int tpw;
+    int cap;
+    float ms;
+};
 
 // Occupancy cap (workgroups per CU).  Without tuning: 8, which measured at
 // or above the uncapped rate for every int8 window class and mode (fewer
 // resident workgroups contend less for LDS banks and the L2).
 constexpr int kDefaultWgPerCu = 8;
-static std::map<uint64_t, int> g_tune_cap;
+constexpr TuneEntry kUntuned = {RFI_SCHED_SPLIT, 1, kDefaultWgPerCu, 0.0f};
 
-int tuned_cap(uint64_t sig)
+static std::mutex g_tune_mu;
+static std::map<std::string, TuneEntry> g_tune;  // key: "<arch>/<signature hex>"
+
+static const char* const kSchedNames[RFI_SCHED_COUNT] = {
+    "auto", "split", "split_persist", "fused", "per_stream", "fused_persist", "split_concurrent",
+    "fused_concurrent", "one_launch", "one_launch_persist"};
+
+static TuneEntry tuned(const std::string& key)
 {
     std::lock_guard<std::mutex> g(g_tune_mu);
-    auto it = g_tune_cap.find(sig);
-    return it == g_tune_cap.end() ? kDefaultWgPerCu : it->second;
+    auto it = g_tune.find(key);
+    return it == g_tune.end() ? kUntuned : it->second;
 }
 
-void record_cap(uint64_t sig, int cap)
+static void record_tuned(const std::string& key, const TuneEntry& e)
 {
     std::lock_guard<std::mutex> g(g_tune_mu);
-    g_tune_cap[sig] = cap;
+    g_tune[key] = e;
+}
+
+// Architecture name of device `dev` up to the first ':' ("gfx950"), cached.
+static std::string device_arch(int dev)
+{
+    static std::mutex mu;
+    static std::map<int, std::string> cache;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(dev);
+    if (it != cache.end()) return it->second;
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        arch = prop.gcnArchName;
+        const size_t c = arch.find(':');
+        if (c != std::string::npos) arch.resize(c);
+    }
+    cache[dev] = arch;
+    return arch;
+}
+
+static std::string tune_key(const std::string& arch, uint64_t sig)
+{
+    char buf[32];
+    std::snprintf(buf, sizeof(buf), "%016llx", (unsigned long long)sig);
+    return arch + "/" + buf;
+}
+
+// Tiny reader for the file rfi_tune_save writes: the objects of the
+// "entries" array, each a flat object of string and number values.
+static bool json_string(const std::string& obj, const char* key, std::string& out)
+{
+    const std::string k = std::string("\"") + key + "\"";
+    size_t p = obj.find(k);
+    if (p == std::string::npos) return false;
+    p = obj.find(':', p + k.size());
+    if (p == std::string::npos) return false;
+    p = obj.find('"', p);
+    if (p == std::string::npos) return false;
+    const size_t q = obj.find('"', p + 1);
+    if (q == std::string::npos) return false;
+    out = obj.substr(p + 1, q - p - 1);
+    return true;
+}
+
+static bool json_number(const std::string& obj, const char* key, double& out)
+{
+    const std::string k = std::string("\"") + key + "\"";
+    size_t p = obj.find(k);
+    if (p == std::string::npos) return false;
+    p = obj.find(':', p + k.size());
+    if (p == std::string::npos) return false;
+    char* end = nullptr;
+    out = std::strtod(obj.c_str() + p + 1, &end);
+    return end != obj.c_str() + p + 1;
+}
+
+int tune_load_file(const char* path)
+{
+    if (!path) return RFI_ERR_INVALID;
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return RFI_ERR_INVALID;
+    std::string text;
+    char buf[4096];
+    size_t n;
+    while ((n = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, n);
+    std::fclose(f);
+    const size_t e = text.find("\"entries\"");
+    if (e == std::string::npos) return RFI_ERR_INVALID;
+    size_t p = text.find('[', e);
+    if (p == std::string::npos) return RFI_ERR_INVALID;
+    std::vector<std::pair<std::string, TuneEntry>> got;
+    for (;;) {
+        const size_t o = text.find_first_of("{]", p + 1);
+        if (o == std::string::npos) return RFI_ERR_INVALID;
+        if (text[o] == ']') break;
+        const size_t c = text.find('}', o);
+        if (c == std::string::npos) return RFI_ERR_INVALID;
+        const std::string obj = text.substr(o, c - o + 1);
+        std::string arch, sig, sched;
+        double tpw = 0, cap = -1, ms = 0;
+        if (!json_string(obj, "arch", arch) || !json_string(obj, "signature", sig) ||
+            !json_string(obj, "schedule", sched) || !json_number(obj, "tiles_per_wg", tpw) ||
+            !json_number(obj, "wg_per_cu", cap))
+            return RFI_ERR_INVALID;
+        (void)json_number(obj, "ms", ms);
+        int si = -1;
+        for (int i = 1; i < RFI_SCHED_COUNT; ++i)
+            if (sched == kSchedNames[i]) si = i;
+        char* end = nullptr;
+        const unsigned long long sv = std::strtoull(sig.c_str(), &end, 16);
+        if (si < 0 || sig.empty() || *end != '\0' || (tpw != 1 && tpw != 2) || cap < 0 || cap > 32)
+            return RFI_ERR_INVALID;
+        got.push_back({tune_key(arch, sv), TuneEntry{si, (int)tpw, (int)cap, (float)ms}});
+        p = c;
+    }
+    for (const auto& kv : got) record_tuned(kv.first, kv.second);
+    return RFI_OK;
+}
+
+int tune_save_file(const char* path)
+{
+    if (!path) return RFI_ERR_INVALID;
+    std::map<std::string, TuneEntry> snap;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        snap = g_tune;
+    }
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return RFI_ERR_INVALID;
+    std::fprintf(f, "{\n \"format\": \"rfimad autotune 1\",\n \"entries\": [");
+    bool first = true;
+    for (const auto& kv : snap) {
+        const size_t slash = kv.first.find('/');
+        const std::string arch = kv.first.substr(0, slash), sig = kv.first.substr(slash + 1);
+        const uint64_t sv = std::strtoull(sig.c_str(), nullptr, 16);
+        // readable form of the signature: dtype, window classes, irregular
+        // windows, noise streams, generic work items
+        std::string classes;
+        const int elem = (int)(sv & 0xFF);
+        for (int c = 0; c < 15; ++c)
+            if (sv & (1ull << (8 + c))) {
+                const int w = elem == 1 ? (512 << c) : 8192;
+                classes += (classes.empty() ? "" : ", ") + std::to_string(w);
+            }
+        std::fprintf(f,
+                     "%s\n  {\"arch\": \"%s\", \"signature\": \"%s\", \"elem_size\": %d, \"window_classes\": [%s], "
+                     "\"irregular_windows\": %s, \"noise\": %s, \"generic_items\": %s, \"schedule\": \"%s\", "
+                     "\"tiles_per_wg\": %d, \"wg_per_cu\": %d, \"ms\": %.6g}",
+                     first ? "" : ",", arch.c_str(), sig.c_str(), elem, classes.c_str(),
+                     (sv >> 23) & 1 ? "true" : "false", (sv >> 32) & 1 ? "true" : "false",
+                     (sv >> 33) & 1 ? "true" : "false", kSchedNames[kv.second.sched], kv.second.tpw, kv.second.cap,
+                     (double)kv.second.ms);
+        first = false;
+    }
+    std::fprintf(f, "\n ]\n}\n");
+    const bool ok = std::fflush(f) == 0;
+    std::fclose(f);
+    if (!ok || std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        return RFI_ERR_INVALID;
+    }
+    return RFI_OK;
+}
+
+// RFI_TUNE_FILE: loaded at the first plan built in the process (a missing
+// file is no error), written again after every autotune.
+static const char* tune_env_file() { return std::getenv("RFI_TUNE_FILE"); }
+
+static void tune_env_load_once()
+{
+    static std::once_flag once;
+    std::call_once(once, [] {
+        const char* f = tune_env_file();
+        if (f && *f) (void)tune_load_file(f);
+    });
 }
 
 }  // namespace rfi
@@ -145,6 +285,7 @@ struct rfi_plan {
     int use_graph = 0;
     int tpw = 0;  // int8 tiles per workgroup in loop-free launches (0: tuned)
     int wg_per_cu = -1;  // occupancy cap (0: none, -1: tuned)
+    std::string tune_key;  // "<arch>/<signature>" of the autotune table
     std::vector<PlanLaunch> launches[RFI_SCHED_COUNT];
     std::vector<GraphEntry> graphs;
     // SPLIT_CONCURRENT: auxiliary streams and fork/join events (created on
@@ -173,12 +314,13 @@ static int tile_class(int elem, int32_t w) { return elem == 1 ? i8_tile_class(w)
 static hipError_t run_launch(const rfi_plan* p, const PlanLaunch& l, const LaunchArgs& base,
                              hipStream_t s)
 {
-    set_wg_per_cu(p->wg_per_cu >= 0 ? p->wg_per_cu : tuned_cap(plan_signature(p)));
+    const TuneEntry te = tuned(p->tune_key);
+    set_wg_per_cu(p->wg_per_cu >= 0 ? p->wg_per_cu : te.cap);
     LaunchArgs a = base;
     a.items = (l.kind == 2 ? p->ditems_fused : p->ditems) + l.first;
     a.n_items = l.count;
     if (p->elem == 1) {
-        if (l.kind == 0) return launch_i8_tiles(l.cls, l.modes, p->tpw > 0 ? p->tpw : tuned_tpw(plan_signature(p)), a, l.grid, s);
+        if (l.kind == 0) return launch_i8_tiles(l.cls, l.modes, p->tpw > 0 ? p->tpw : te.tpw, a, l.grid, s);
         if (l.kind == 1) return launch_i8_generic(a, l.modes, l.grid, s, l.small);
         return launch_i8_fused(l.modes, a, l.grid, s);
     }
@@ -267,6 +409,20 @@ static void build_launches(rfi_plan* p)
             f.grid = (int)std::min<int64_t>(e - b, persistent_grid(elem, -1, modes, true));
             p->launches[RFI_SCHED_FUSED_PERSIST].push_back(f);
             b = e;
+        }
+    }
+    // One launch over every item of every class and mode (mode-major
+    // order), one workgroup per item or a persistent grid: the whole batch
+    // as a single kernel, compiled for the modes present.
+    {
+        const int64_t nf = (int64_t)p->hitems_fused.size();
+        if (nf > 0) {
+            int modes = 0;
+            for (const Item& it : p->hitems_fused) modes |= 1 << p->M[it.stream];
+            PlanLaunch f{2, 0, -1, modes, 0, nf, clamp_grid(nf)};
+            p->launches[RFI_SCHED_ONE_LAUNCH].push_back(f);
+            f.grid = (int)std::min<int64_t>(nf, persistent_grid(elem, -1, modes, true));
+            p->launches[RFI_SCHED_ONE_LAUNCH_PERSIST].push_back(f);
         }
     }
     // One ordinary launch per stream and kind (the plain baseline).
@@ -389,6 +545,8 @@ int plan_build(int elem, int32_t n, const int64_t* L, const int32_t* W, const fl
         }
     }
     build_launches(p.get());
+    p->tune_key = tune_key(device_arch(p->device), plan_signature(p.get()));
+    tune_env_load_once();
     *out = p.release();
     return RFI_OK;
 }
@@ -426,7 +584,7 @@ void plan_free(rfi_plan* p)
 static int effective_schedule(const rfi_plan* p)
 {
     if (p->schedule != RFI_SCHED_AUTO) return p->schedule;
-    return tuned_schedule(plan_signature(p));
+    return tuned(p->tune_key).sched;
 }
 
 // Issues a schedule's launches on s; SPLIT_CONCURRENT forks them over the
@@ -477,9 +635,9 @@ int plan_execute(rfi_plan* p, const void* x, void* y, rfi_window_stats* st, hipS
     base.no_stats = st ? 0 : 1;
     const auto& ls = p->launches[sched];
     if (p->use_graph && s != nullptr && !ls.empty()) {
-        const uint64_t sig = plan_signature(p);
-        const int tpw = p->tpw > 0 ? p->tpw : tuned_tpw(sig);
-        const int cap = p->wg_per_cu >= 0 ? p->wg_per_cu : tuned_cap(sig);
+        const TuneEntry te = tuned(p->tune_key);
+        const int tpw = p->tpw > 0 ? p->tpw : te.tpw;
+        const int cap = p->wg_per_cu >= 0 ? p->wg_per_cu : te.cap;
         for (auto& g : p->graphs) {
             if (g.x == base.x_base && g.y == base.y_base && g.st == base.stats_base && g.s == s &&
                 g.sched == sched && g.tpw == tpw && g.cap == cap) {
@@ -669,7 +827,9 @@ int rfi_plan_autotune(rfi_plan* plan, const void* x, void* y, rfi_window_stats* 
                           {RFI_SCHED_SPLIT, 2, 8}, {RFI_SCHED_SPLIT_PERSIST, 1, 8},
                           {RFI_SCHED_FUSED, 1, 8}, {RFI_SCHED_FUSED, 1, 0},
                           {RFI_SCHED_FUSED_PERSIST, 1, 0}, {RFI_SCHED_SPLIT_CONCURRENT, 1, 8},
-                          {RFI_SCHED_SPLIT_CONCURRENT, 1, 0}, {RFI_SCHED_FUSED_CONCURRENT, 1, 8}};
+                          {RFI_SCHED_SPLIT_CONCURRENT, 1, 0}, {RFI_SCHED_FUSED_CONCURRENT, 1, 8},
+                          {RFI_SCHED_ONE_LAUNCH, 1, 8}, {RFI_SCHED_ONE_LAUNCH, 1, 0},
+                          {RFI_SCHED_ONE_LAUNCH_PERSIST, 1, 0}};
     for (const Cand& cand : cands) {
         const int c = cand.sched;
         if (plan->launches[c].empty()) continue;
@@ -707,9 +867,9 @@ int rfi_plan_autotune(rfi_plan* plan, const void* x, void* y, rfi_window_stats* 
     plan->tpw = best_tpw;
     plan->wg_per_cu = best_cap;
     drop_graphs(plan);
-    record_schedule(plan_signature(plan), best);
-    record_tpw(plan_signature(plan), best_tpw);
-    record_cap(plan_signature(plan), best_cap);
+    record_tuned(plan->tune_key, TuneEntry{best, best_tpw, best_cap, best_t});
+    if (const char* f = tune_env_file())
+        if (*f && tune_save_file(f) != RFI_OK) return RFI_ERR_INVALID;
     if (best_schedule) *best_schedule = best;
     if (best_ms) *best_ms = best_t;
     return RFI_OK;
@@ -720,6 +880,10 @@ int rfi_plan_destroy(rfi_plan* plan)
     plan_free(plan);
     return RFI_OK;
 }
+
+int rfi_tune_save(const char* path) { return rfi::tune_save_file(path); }
+
+int rfi_tune_load(const char* path) { return rfi::tune_load_file(path); }
 
 }  // extern "C"
 

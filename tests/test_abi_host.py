@@ -114,3 +114,51 @@ def test_profile_summaries_parse():
     summ = profiling.load_summary(os.path.join(root, "profiles", "i8_w4096_plain_scale.md"))
     assert summ["calibration"]["copy_bytes"] > 0
     assert len(summ["kernel_source_sha256"]) == 64
+
+
+def test_tune_table_json_round_trip(tmp_path):
+    """rfi_tune_load reads the JSON that rfi_tune_save writes (host only):
+    hand-written entries come back with the same keys and choices, malformed
+    files are refused whole."""
+    import json
+    src = tmp_path / "tune_in.json"
+    entries = [
+        {"arch": "gfx950", "signature": "0000000300003e01", "schedule": "fused", "tiles_per_wg": 1,
+         "wg_per_cu": 8, "ms": 0.23},
+        {"arch": "gfx950", "signature": "0000000000000802", "schedule": "one_launch_persist",
+         "tiles_per_wg": 2, "wg_per_cu": 0, "ms": 0.5},
+        {"arch": "gfx942", "signature": "0000000000000801", "schedule": "split", "tiles_per_wg": 1,
+         "wg_per_cu": 6, "ms": 1.0},
+    ]
+    src.write_text(json.dumps({"format": "rfimad autotune 1", "entries": entries}, indent=1))
+    rfi.tune_load(str(src))
+    out = tmp_path / "tune_out.json"
+    rfi.tune_save(str(out))
+    got = json.loads(out.read_text())["entries"]
+    keyed = {(e["arch"], e["signature"]): e for e in got}
+    for e in entries:
+        g = keyed[(e["arch"], e["signature"])]
+        for k in ("schedule", "tiles_per_wg", "wg_per_cu"):
+            assert g[k] == e[k], (e, g)
+        assert g["ms"] == pytest.approx(e["ms"], rel=1e-5)
+    # readable fields of the signature: int8, classes 512..16384 but 1024
+    g = keyed[("gfx950", "0000000300003e01")]
+    assert g["elem_size"] == 1 and g["window_classes"] == [1024, 2048, 4096, 8192, 16384]
+    assert g["noise"] is True and g["generic_items"] is True and g["irregular_windows"] is False
+    # a second save of the loaded file is identical
+    out2 = tmp_path / "tune_out2.json"
+    rfi.tune_load(str(out))
+    rfi.tune_save(str(out2))
+    assert json.loads(out2.read_text()) == json.loads(out.read_text())
+    # malformed: unknown schedule, bad tiles per workgroup, not a table, missing file
+    for bad in ('{"entries": [{"arch": "gfx950", "signature": "1", "schedule": "nope", '
+                '"tiles_per_wg": 1, "wg_per_cu": 8}]}',
+                '{"entries": [{"arch": "gfx950", "signature": "1", "schedule": "fused", '
+                '"tiles_per_wg": 3, "wg_per_cu": 8}]}',
+                '[1, 2, 3]'):
+        f = tmp_path / "bad.json"
+        f.write_text(bad)
+        with pytest.raises(rfi.RfiError):
+            rfi.tune_load(str(f))
+    with pytest.raises(rfi.RfiError):
+        rfi.tune_load(str(tmp_path / "missing.json"))

@@ -57,7 +57,8 @@ def test_all_schedules(gpu):
              synth.StreamSpec(9000, 2000, 2.5, rfi.CLIP, 200.0, 0.01, 32, 32, "i16")]
     x = synth.gen_packed(specs, seed=3, tag=22)
     ref = None
-    for sched in ("split", "split_persist", "fused", "fused_persist", "per_stream", "split_concurrent", "fused_concurrent"):
+    for sched in ("split", "split_persist", "fused", "fused_persist", "per_stream", "split_concurrent", "fused_concurrent",
+                  "one_launch", "one_launch_persist"):
         for graph in (False, True):
             y, st = gpu_run(x, specs, 1, gpu, schedule=sched, graph=graph, repeat=2)
             if ref is None:

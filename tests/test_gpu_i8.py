@@ -93,7 +93,8 @@ def test_mixed_batch_all_schedules_and_graphs(gpu):
     specs += [synth.StreamSpec(50000, 3000, 3.0, rfi.NOISE, 10.0, 0.01, 8, 64)]
     x = synth.gen_packed(specs, seed=4, tag=4)
     ref = None
-    for sched in ("split", "split_persist", "fused", "fused_persist", "per_stream", "split_concurrent", "fused_concurrent"):
+    for sched in ("split", "split_persist", "fused", "fused_persist", "per_stream", "split_concurrent", "fused_concurrent",
+                  "one_launch", "one_launch_persist"):
         for graph in (False, True):
             y, st = gpu_run(x, specs, 9, gpu, schedule=sched, graph=graph, repeat=2)
             if ref is None:
@@ -280,3 +281,71 @@ def test_generic_register_path_edges(gpu, W):
     check_against_oracle(x, specs, 13, y, st)
     y, st = gpu_run(x, specs, 13, gpu, schedule="fused", graph=True)
     check_against_oracle(x, specs, 13, y, st)
+
+
+_CHILD = r"""
+import json, os, sys
+sys.path.insert(0, sys.argv[1])
+import paper_1710_08576_amd as rfi
+a = json.loads(sys.argv[2])
+if a["load"]:
+    rfi.tune_load(a["load"])
+p = rfi.Plan(1, a["L"], a["W"], a["K"], a["M"], seed=5)
+print(json.dumps({"schedule": p.schedule()}))
+p.close()
+"""
+
+
+def test_autotune_table_persists_across_processes(gpu, tmp_path):
+    """A tuned schedule saved as JSON is picked up by a new process without
+    re-tuning, by an explicit load and through RFI_TUNE_FILE."""
+    import json
+    import os
+    import subprocess
+    import sys
+    specs = synth.batching(n_streams=10, lo=1 << 15, hi=1 << 17, seed=21)
+    x = synth.gen_packed(specs, seed=21, tag=21)
+    L, W, K, M = unpack(specs)
+    xd = x.to(gpu)
+    p = rfi.Plan(1, L, W, K, M, seed=5)
+    yd = torch.empty_like(xd)
+    st = torch.empty((p.n_windows, 4), dtype=torch.int32, device=gpu)
+    best, _ = p.autotune(xd, yd, st, iters=2)
+    torch.cuda.synchronize()
+    check_against_oracle(x, specs, 5, yd.cpu().numpy(), rfi.stats_numpy(st), check_padding=False)
+    gen = p.info()["generic"]
+    p.close()
+    path = str(tmp_path / "tune.json")
+    rfi.tune_save(path)
+    # this plan's signature: element size, window classes, irregular
+    # windows, noise streams, generic items
+    classes = {512: 0, 1024: 1, 2048: 2, 4096: 3, 8192: 4, 16384: 5}
+    sig = 1
+    for w, m in zip(W, M):
+        sig |= 1 << (8 + classes.get(w, 15))
+        sig |= (1 << 32) if m == rfi.NOISE else 0
+    sig |= (1 << 33) if gen else 0
+    table = json.loads(open(path).read())
+    mine = [e for e in table["entries"] if e["signature"] == "%016x" % sig]
+    assert len(mine) == 1 and mine[0]["schedule"] == {v: k for k, v in rfi.SCHEDULES.items()}[best]
+    # a copy whose entry names another schedule: the new process must follow it
+    other = "one_launch_persist" if best != rfi.SCHEDULES["one_launch_persist"] else "fused"
+    mine[0]["schedule"] = other
+    path2 = str(tmp_path / "tune_edited.json")
+    with open(path2, "w") as f:
+        json.dump(table, f)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    args = {"L": L, "W": W, "K": K, "M": M}
+    clean = {k: v for k, v in os.environ.items() if k != "RFI_TUNE_FILE"}
+
+    def child(load, env):
+        out = subprocess.run([sys.executable, "-c", _CHILD, root, json.dumps({**args, "load": load})],
+                             capture_output=True, text=True, timeout=120, env=env)
+        assert out.returncode == 0, out.stderr
+        return json.loads(out.stdout.strip().splitlines()[-1])["schedule"]
+
+    assert child(None, clean) == rfi.SCHEDULES["split"]  # untuned
+    assert child(path, clean) == best
+    assert child(path2, clean) == rfi.SCHEDULES[other]
+    assert child(None, dict(clean, RFI_TUNE_FILE=path)) == best
+    assert child(None, dict(clean, RFI_TUNE_FILE=path2)) == rfi.SCHEDULES[other]

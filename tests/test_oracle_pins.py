@@ -18,6 +18,8 @@ import torch
 import oracle
 from paper_1710_08576_amd import synth
 
+from _expect import rounded_gaussian_pmf
+
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
@@ -316,7 +318,7 @@ def test_int16_gaussian_closed_forms():
 def test_int8_discrete_expectations(sigma):
     """int8 quantisation moves MAD and the flag rate off the continuous values;
     compare with the exact discrete expectation from the rounded-Gaussian pmf."""
-    pmf = np.array(synth.rounded_gaussian_pmf(sigma, -128, 127))
+    pmf = np.array(rounded_gaussian_pmf(sigma, -128, 127))
     vals = np.arange(-128, 128)
     # population median is 0 by symmetry; population MAD: smallest d with P(|X|<=d) >= 1/2
     cum = np.array([pmf[np.abs(vals) <= d].sum() for d in range(128)])
