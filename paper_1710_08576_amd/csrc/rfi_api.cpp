@@ -324,7 +324,7 @@ static hipError_t run_launch(const rfi_plan* p, const PlanLaunch& l, const Launc
         if (l.kind == 1) return launch_i8_generic(a, l.modes, l.grid, s, l.small);
         return launch_i8_fused(l.modes, a, l.grid, s);
     }
-    if (l.kind == 0) return launch_i16_tiles(l.cls, a, l.grid, s);
+    if (l.kind == 0) return launch_i16_tiles(l.cls, l.modes, a, l.grid, s);
     if (l.kind == 1) return launch_i16_generic(a, l.grid, s);
     return launch_i16_fused(a, l.grid, s);
 }

@@ -144,6 +144,12 @@ __device__ __forceinline__ void gstore(T* p, T v)
 // number of live registers in long unrolled sequences).
 __device__ __forceinline__ void sched_fence() { __builtin_amdgcn_sched_barrier(0); }
 
+// Pins a wave-uniform running sum in a scalar register at this point of
+// the program (an empty asm statement, no instruction): without it the
+// compiler reassociates a chain of ballot popcounts and keeps every ballot
+// mask alive until the end of the chain.
+__device__ __forceinline__ void pin_sgpr(uint32_t& x) { asm volatile("" : "+s"(x)); }
+
 // ------------------------------------------------------------------------
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
 // 64x64->128 multiplies; the key is bumped by the two Weyl constants after
@@ -285,6 +291,30 @@ __device__ __forceinline__ uint32_t pk_absdiff_i16(uint32_t a, uint32_t b)
     const ushort2v hi = __builtin_bit_cast(ushort2v, __builtin_elementwise_max(x, y));
     const ushort2v lo = __builtin_bit_cast(ushort2v, __builtin_elementwise_min(x, y));
     return __builtin_bit_cast(uint32_t, (ushort2v)(hi - lo));
+}
+
+// Unsigned 16-bit lane arithmetic on two halves (v_pk_* instructions).
+__device__ __forceinline__ uint32_t pk_sub_u16(uint32_t a, uint32_t b)
+{
+    return __builtin_bit_cast(uint32_t, (ushort2v)(__builtin_bit_cast(ushort2v, a) - __builtin_bit_cast(ushort2v, b)));
+}
+
+__device__ __forceinline__ uint32_t pk_min_u16(uint32_t a, uint32_t b)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(__builtin_bit_cast(ushort2v, a),
+                                                                  __builtin_bit_cast(ushort2v, b)));
+}
+
+__device__ __forceinline__ uint32_t pk_shl2_u16(uint32_t a)
+{
+    return __builtin_bit_cast(uint32_t, (ushort2v)(__builtin_bit_cast(ushort2v, a) << (ushort2v){2, 2}));
+}
+
+// 0xFFFF in every 16-bit half of `diff` that is non-zero: min(half, 1)
+// subtracted from zero.
+__device__ __forceinline__ uint32_t pk_mask_nonzero_u16(uint32_t diff)
+{
+    return pk_sub_u16(0u, pk_umin1(diff));
 }
 
 __device__ __forceinline__ uint32_t rep_i16(int v)

@@ -133,7 +133,7 @@ hipError_t launch_i8_tiles(int cls, int modes, int tpw, const LaunchArgs& a, int
 // one workgroup per item); 0: 256-thread workgroups.
 hipError_t launch_i8_generic(const LaunchArgs& a, int modes, int grid, hipStream_t s, int small_nt = 0);
 hipError_t launch_i8_fused(int modes, const LaunchArgs& a, int grid, hipStream_t s);
-hipError_t launch_i16_tiles(int cls, const LaunchArgs& a, int grid, hipStream_t s);
+hipError_t launch_i16_tiles(int cls, int modes, const LaunchArgs& a, int grid, hipStream_t s);
 hipError_t launch_i16_generic(const LaunchArgs& a, int grid, hipStream_t s);
 hipError_t launch_i16_fused(const LaunchArgs& a, int grid, hipStream_t s);
 

@@ -1004,13 +1004,20 @@ __device__ __forceinline__ uint2 noise_quad_i16(uint64_t j0, uint64_t seed, uint
 // copies did.
 constexpr int kI16Reps = 1;  // replicas of the coarse histogram (replica = lane % R)
 
+// Values of the full-resolution band of the fast path (one bin each).
+constexpr int kI16Band = 4096;
+
 struct I16TileSmem {
-    __align__(16) uint32_t h[4096 * kI16Reps];  // coarse counts: h[bin * R + rep]
+    // radix path: coarse counts h[bin * R + rep]; band path: one bin per
+    // value of the band, then the bin of the samples above it
+    __align__(16) uint32_t h[kI16Band + 16];
     uint32_t fine[2][16];  // fine digit inside the selected coarse bin
     uint32_t part[4];      // per-wave totals of the block scan
     int sel[2];            // selected coarse bin, count below it
     uint32_t flagged;
     uint32_t mad_below;    // samples with |x - m| below the MAD bracket
+    uint32_t est[4];       // band path: the waves' median estimates
+    uint32_t below;        // band path: samples below the band
     uint32_t noise_counts[4];
     __device__ NoiseScratch noise()
     {
@@ -1121,33 +1128,21 @@ __device__ __forceinline__ int i16_fine_select(const uint32_t* f, uint32_t need)
 __device__ __forceinline__ int lo16(uint32_t v) { return (int)(int16_t)(v & 0xFFFFu); }
 __device__ __forceinline__ int hi16(uint32_t v) { return (int)(int16_t)(v >> 16); }
 
-// W = 8192 int16 samples = 16 KiB = one window per workgroup tile.
-__device__ void i16_tile_8192(const StreamView& d, int64_t first, uint64_t seed, I16TileSmem& sm)
+// int16 median and MAD by radix digits (the general path): a 12-bit coarse
+// digit histogram, the coarse bin of the median, a 4-bit fine digit inside
+// it, and the MAD from a 16-value bracket read off the coarse counts plus
+// one filtered pass over |x - m|.  v: the tile's samples (16 dwords per
+// lane); starts with a barrier (the scratch may still be read).
+__device__ void i16_select_radix(const uint32_t (&v)[16], I16TileSmem& sm, int& m_out, int& D_out)
 {
     constexpr int W = 8192;
     constexpr int R = kI16Reps;
     const int lane = lane_id();
     const int tid = (int)threadIdx.x;
-    const int wbase = (tid >> 6) * 4096;  // bytes
-    const uint8_t* xt = reinterpret_cast<const uint8_t*>(static_cast<const int16_t*>(d.x) + first) + wbase + lane * 16;
-    uint8_t* yt = reinterpret_cast<uint8_t*>(static_cast<int16_t*>(d.y) + first) + wbase + lane * 16;
-
-    uint32_t v[16];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const uint4 t = gload16_nt(xt + i * 1024);
-        v[4 * i] = t.x;
-        v[4 * i + 1] = t.y;
-        v[4 * i + 2] = t.z;
-        v[4 * i + 3] = t.w;
-    }
-    __syncthreads();  // the previous tile is done with the scratch
+    __syncthreads();
     zero_words(sm.h, 4096 * R, tid, kBlock);
     if (tid < 8) reinterpret_cast<uint4*>(&sm.fine[0][0])[tid] = make_uint4(0, 0, 0, 0);
-    if (tid == 0) {
-        sm.flagged = 0;
-        sm.mad_below = 0;
-    }
+    if (tid == 0) sm.mad_below = 0;
     __syncthreads();
 
     const uint32_t rep = (uint32_t)(lane & (R - 1));
@@ -1181,26 +1176,179 @@ __device__ void i16_tile_8192(const StreamView& d, int64_t first, uint64_t seed,
     const int m = ((b1 << 4) | i16_fine_select(sm.fine[0], need - below1)) - 32768;
     // MAD: bracket [dlo, dlo + 15] from the coarse counts of x, then the
     // exact rank inside it from |x - m| of the samples (no second histogram
-    // over 4096 bins).
+    // over 4096 bins).  The samples below the bracket are counted from
+    // ballots (wave-uniform sums).
     const int dlo = i16_mad_lower(sm, m + 32768, need);
     const uint32_t m2 = rep_i16(m);
+    const uint32_t dlo2 = rep_i16(dlo);
     uint32_t nbelow = 0;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const uint32_t dq = pk_absdiff_i16(v[q], m2);
-        const uint32_t d0 = dq & 0xFFFFu, d1 = dq >> 16;
-        nbelow += (d0 < (uint32_t)dlo ? 1u : 0u) + (d1 < (uint32_t)dlo ? 1u : 0u);
-        const uint32_t r0 = d0 - (uint32_t)dlo, r1 = d1 - (uint32_t)dlo;  // wraps when below
-        const bool in0 = r0 < 16u, in1 = r1 < 16u;
+        nbelow += (uint32_t)__popcll(__ballot((dq & 0xFFFFu) < (uint32_t)dlo)) +
+                  (uint32_t)__popcll(__ballot(dq < ((uint32_t)dlo << 16)));
+        pin_sgpr(nbelow);
+        const uint32_t r = pk_sub_u16(dq, dlo2);  // wraps when below
+        const bool in0 = (r & 0xFFFFu) < 16u, in1 = r < (16u << 16);
         if (__ballot(in0 || in1) != 0) {
-            if (in0) atomicAdd(&sm.fine[1][r0], 1u);
-            if (in1) atomicAdd(&sm.fine[1][r1], 1u);
+            if (in0) atomicAdd(&sm.fine[1][r & 0xFu], 1u);
+            if (in1) atomicAdd(&sm.fine[1][(r >> 16) & 0xFu], 1u);
         }
     }
-    nbelow = group_sum<64>(nbelow);
-    if (lane == 63) atomicAdd(&sm.mad_below, nbelow);
+    if (lane == 0) atomicAdd(&sm.mad_below, nbelow);
     __syncthreads();
-    const int D = dlo + i16_fine_select(sm.fine[1], need - sm.mad_below);
+    m_out = m;
+    D_out = dlo + i16_fine_select(sm.fine[1], need - sm.mad_below);
+}
+
+// int16 median and MAD from one full-resolution histogram (the fast path).
+// The band of kI16Band consecutive values of u = x + 32768 centred on an
+// estimate of the median (the lower median of the four waves' sample
+// medians, each over 64 of its samples) is counted at one bin per value,
+// samples above it in one extra bin, samples below it by ballots.  The
+// median is then read off the cumulative counts, and the MAD by a search
+// over d of N(d) = #{m - d <= u <= m + d}, also read off them.  Returns
+// false (every thread alike) when the median lies outside the band or the
+// MAD reaches past it; the caller then selects by radix digits.  Exact
+// either way: only where the counts are, not what they are, depends on
+// the estimate.
+__device__ bool i16_select_band(const uint32_t (&v)[16], I16TileSmem& sm, int& m_out, int& D_out)
+{
+    constexpr uint32_t need = 4096;  // rank floor((8192 - 1) / 2), 1-based
+    const int lane = lane_id();
+    const int tid = (int)threadIdx.x, wave = tid >> 6;
+    // This wave's estimate: the lower median of 64 of its samples (low
+    // halves of dwords 0, 5, 10, 15 in lane groups of 16), by a bitwise
+    // search on ballot counts.
+    const uint32_t pick = lane < 16 ? v[0] : lane < 32 ? v[5] : lane < 48 ? v[10] : v[15];
+    const uint32_t us = (pick ^ 0x8000u) & 0xFFFFu;
+    uint32_t est = 0;
+#pragma unroll
+    for (int b = 15; b >= 0; --b) {
+        const uint32_t t = est | (1u << b);
+        est = __popcll(__ballot(us < t)) < 32 ? t : est;
+    }
+    __syncthreads();  // the previous tile is done with the scratch
+    zero_words(sm.h, kI16Band + 16, tid, kBlock);
+    if (lane == 0) sm.est[wave] = est;
+    if (tid == 0) {
+        sm.below = 0;
+        sm.flagged = 0;  // added to once the tile is replaced
+    }
+    __syncthreads();
+    uint32_t e[4] = {sm.est[0], sm.est[1], sm.est[2], sm.est[3]};
+    // lower median of the four estimates: the second smallest
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3 - i; ++j) {
+            const uint32_t lo = min(e[j], e[j + 1]), hi = max(e[j], e[j + 1]);
+            e[j] = lo;
+            e[j + 1] = hi;
+        }
+    const int base = min(max((int)e[1] - kI16Band / 2, 0), 65536 - kI16Band);
+    // u - base in each 16-bit half is x - (base - 32768) modulo 2^16.
+    const uint32_t xb = (uint32_t)(base ^ 0x8000) & 0xFFFFu;
+    const uint32_t xb2 = xb | (xb << 16);
+    const int xs = base - 32768;  // the band's first sample value
+    uint32_t below = 0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const uint32_t x = v[q];
+        // byte offset of each half's bin: (u - base) clamped to the extra
+        // bin kI16Band, times 4
+        const uint32_t t = pk_shl2_u16(pk_min_u16(pk_sub_u16(x, xb2), (uint32_t)kI16Band * 0x10001u));
+        atomicAdd(reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(sm.h) + (t & 0xFFFFu)), 1u);
+        atomicAdd(reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(sm.h) + (t >> 16)), 1u);
+        below += (uint32_t)__popcll(__ballot((int)(int16_t)(x & 0xFFFFu) < xs)) +
+                 (uint32_t)__popcll(__ballot((int32_t)x < xs * 65536));
+        pin_sgpr(below);
+        sched_fence();
+    }
+    if (lane == 0) atomicAdd(&sm.below, below);
+    __syncthreads();
+    const uint32_t bl = sm.below;
+    // Thread t scans bins 16t .. 16t + 15, and rewrites them as inclusive
+    // cumulative counts of the band (without the samples below it).
+    uint32_t c[16];
+#pragma unroll
+    for (int j = 0; j < 16; j += 4) {
+        const uint4 w = *reinterpret_cast<const uint4*>(sm.h + tid * 16 + j);
+        c[j] = w.x;
+        c[j + 1] = w.y;
+        c[j + 2] = w.z;
+        c[j + 3] = w.w;
+    }
+#pragma unroll
+    for (int j = 1; j < 16; ++j) c[j] += c[j - 1];
+    const uint32_t incl = group_incl_scan<64>(c[15]);
+    if (lane == 63) sm.part[wave] = incl;
+    __syncthreads();
+    uint32_t off = 0, inside = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        off += w < wave ? sm.part[w] : 0u;
+        inside += sm.part[w];
+    }
+    const uint32_t excl = bl + off + incl - c[15];
+    if (excl < need && need <= excl + c[15]) {
+        int cnt = 0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) cnt += excl + c[j] < need ? 1 : 0;
+        sm.sel[0] = tid * 16 + cnt;
+    }
+#pragma unroll
+    for (int j = 0; j < 16; j += 4)
+        *reinterpret_cast<uint4*>(sm.h + tid * 16 + j) =
+            make_uint4(excl + c[j], excl + c[j + 1], excl + c[j + 2], excl + c[j + 3]);
+    __syncthreads();
+    if (bl >= need || bl + inside < need) return false;  // the median is outside the band
+    const int m = base + sm.sel[0];
+    // C(u') = #{u <= u'} for u' in [base - 1, base + kI16Band - 1]
+    auto C = [&](int u) -> uint32_t { return u < base ? bl : sm.h[u - base]; };
+    const int dwin = min(base + kI16Band - 1 - m, m - base);
+    if (C(m + dwin) - C(m - dwin - 1) < need) return false;  // the MAD reaches past the band
+    // smallest d in [0, dwin] with N(d) >= need: 64-way search, each lane
+    // testing the right end of its sub-range
+    int lo = 0, span = dwin + 1;
+    while (span > 1) {
+        const int step = (span + 63) >> 6;
+        const int right = min(lo + (lane + 1) * step - 1, lo + span - 1);
+        const bool ok = lo + lane * step < lo + span && C(m + right) - C(m - right - 1) >= need;
+        const int f = (int)__builtin_ctzll(__ballot(ok));  // the last sub-range always qualifies
+        const int nlo = lo + f * step;
+        span = min(step, lo + span - nlo);
+        lo = nlo;
+    }
+    m_out = m - 32768;
+    D_out = lo;
+    return true;
+}
+
+// W = 8192 int16 samples = 16 KiB = one window per workgroup tile.
+// MODES: bit m set if the launch has windows in mode m (one bit: the mode
+// is fixed at compile time).
+template <int MODES>
+__device__ void i16_tile_8192(const StreamView& d, int64_t first, uint64_t seed, I16TileSmem& sm)
+{
+    constexpr int W = 8192;
+    const int lane = lane_id();
+    const int tid = (int)threadIdx.x;
+    const int wbase = (tid >> 6) * 4096;  // bytes
+    const uint8_t* xt = reinterpret_cast<const uint8_t*>(static_cast<const int16_t*>(d.x) + first) + wbase + lane * 16;
+    uint8_t* yt = reinterpret_cast<uint8_t*>(static_cast<int16_t*>(d.y) + first) + wbase + lane * 16;
+
+    uint32_t v[16];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint4 t = gload16_nt(xt + i * 1024);
+        v[4 * i] = t.x;
+        v[4 * i + 1] = t.y;
+        v[4 * i + 2] = t.z;
+        v[4 * i + 3] = t.w;
+    }
+    int m, D;
+    if (!i16_select_band(v, sm, m, D)) i16_select_radix(v, sm, m, D);
 
     float sig;
     const float t = threshold_of(D, d.k, sig);
@@ -1208,26 +1356,28 @@ __device__ void i16_tile_8192(const StreamView& d, int64_t first, uint64_t seed,
     const int lo = max(m - T, -32768), hi = min(m + T, 32767);
     const uint32_t lo2 = rep_i16(lo), hi2 = rep_i16(hi);
     const int sq8 = (int)__fmul_rn(sig, 256.0f);
-    const int mode = d.mode;
-    uint32_t nflag = 0;
-    uint32_t cf = 0;  // bit 2i + h: dwords 2h, 2h + 1 of slot i hold a flagged sample
+    const int mode = MODES == 1 ? RFI_MODE_ZERO : MODES == 2 ? RFI_MODE_CLIP : MODES == 4 ? RFI_MODE_NOISE : d.mode;
+    uint32_t nflag = 0;  // wave-uniform (ballot counts)
+    uint32_t cf = 0;     // bit 2i + h: dwords 2h, 2h + 1 of slot i hold a flagged sample
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            uint32_t t = 0;
+            uint32_t any = 0;
 #pragma unroll
             for (int j = 2 * h; j < 2 * h + 2; ++j) {
                 const int q = 4 * i + j;
                 const uint32_t x = v[q];
                 const uint32_t c = pk_clamp_i16(x, lo2, hi2);
-                const uint32_t mk = nonzero_half_mask(c ^ x);
-                nflag += __popc(mk) >> 4;
-                t |= mk;
+                const uint32_t diff = c ^ x;  // non-zero halves: flagged samples
+                nflag += (uint32_t)__popcll(__ballot((diff & 0xFFFFu) != 0)) +
+                         (uint32_t)__popcll(__ballot(diff > 0xFFFFu));
+                pin_sgpr(nflag);
                 if (mode == RFI_MODE_CLIP) v[q] = c;
-                else if (mode == RFI_MODE_ZERO) v[q] = x & ~mk;
+                else if (mode == RFI_MODE_ZERO) v[q] = x & ~pk_mask_nonzero_u16(diff);
+                else any |= diff;
             }
-            cf |= (t != 0 ? 1u : 0u) << (2 * i + h);
+            if (mode == RFI_MODE_NOISE) cf |= (any != 0 ? 1u : 0u) << (2 * i + h);
         }
     }
     if (mode == RFI_MODE_NOISE) {
@@ -1246,7 +1396,6 @@ __device__ void i16_tile_8192(const StreamView& d, int64_t first, uint64_t seed,
 #pragma unroll
     for (int i = 0; i < 4; ++i)
         gstore16_nt(yt + i * 1024, make_uint4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]));
-    nflag = group_sum<64>(nflag);
     if (lane == 0) atomicAdd(&sm.flagged, nflag);
     __syncthreads();
     if (tid == 0 && d.stats) {
@@ -1489,14 +1638,14 @@ __global__ __launch_bounds__(kBlock) void k_i8_fused(LaunchArgs a)
     });
 }
 
-template <bool PERSIST>
+template <bool PERSIST, int MODES>
 __global__ __launch_bounds__(kBlock) void k_i16_tiles(LaunchArgs a)
 {
     __shared__ I16TileSmem sm;
     for_items<PERSIST>(a, [&](int64_t it) {
         const Item item = a.items[it];
         const StreamView d = resolve(a.streams[item.stream], a);
-        i16_tile_8192(d, item.first, a.seed, sm);
+        i16_tile_8192<MODES>(d, item.first, a.seed, sm);
     });
 }
 
@@ -1524,7 +1673,7 @@ __global__ __launch_bounds__(kBlock) void k_i16_fused(LaunchArgs a)
         const Item item = a.items[it];
         const StreamView d = resolve(a.streams[item.stream], a);
         if (item.kind == kItemGeneric) i16_generic(d, item.first, a.seed, sm.g);
-        else i16_tile_8192(d, item.first, a.seed, sm.t);
+        else i16_tile_8192<7>(d, item.first, a.seed, sm.t);
     });
 }
 
@@ -2032,10 +2181,21 @@ hipError_t launch_i8_fused(int modes, const LaunchArgs& a, int grid, hipStream_t
 {
     return launch(grid < a.n_items ? i8_fused_kernel<true>(modes) : i8_fused_kernel<false>(modes), a, grid, s);
 }
-hipError_t launch_i16_tiles(int cls, const LaunchArgs& a, int grid, hipStream_t s)
+template <bool PERSIST>
+static void (*i16_tile_kernel(int modes))(LaunchArgs)
+{
+    switch (modes) {
+        case 1: return k_i16_tiles<PERSIST, 1>;
+        case 2: return k_i16_tiles<PERSIST, 2>;
+        case 4: return k_i16_tiles<PERSIST, 4>;
+        default: return k_i16_tiles<PERSIST, 7>;
+    }
+}
+
+hipError_t launch_i16_tiles(int cls, int modes, const LaunchArgs& a, int grid, hipStream_t s)
 {
     if (cls != 0) return hipErrorInvalidValue;
-    return launch(RFI_PICK(k_i16_tiles, a, grid), a, grid, s);
+    return launch(grid < a.n_items ? i16_tile_kernel<true>(modes) : i16_tile_kernel<false>(modes), a, grid, s);
 }
 hipError_t launch_i16_generic(const LaunchArgs& a, int grid, hipStream_t s)
 {
@@ -2159,7 +2319,7 @@ int persistent_grid(int elem_size, int cls, int modes, bool fused)
     } else {
         if (fused) k = k_i16_fused<true>;
         else if (cls < 0) k = k_i16_generic<true>;
-        else k = k_i16_tiles<true>;
+        else k = i16_tile_kernel<true>(modes);
     }
     int per_cu = 0;
     if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kBlock, 0) != hipSuccess || per_cu < 1)

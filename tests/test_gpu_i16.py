@@ -52,6 +52,46 @@ def test_degenerate(gpu, mode):
     check_against_oracle(x, specs, 3, y, st)
 
 
+def _band_and_radix_windows(rng, n_each=3):
+    """W 8192 windows of every kind the tile's two selection paths see: the
+    full-resolution band around the estimated median (narrow and moderate
+    spreads, bursts, a median far from zero) and the radix fallback (median
+    or MAD outside the band: wide spreads, uniform, bimodal, a level step
+    inside the window)."""
+    W = 8192
+    g = lambda mu, sd: np.clip(np.round(rng.normal(mu, sd, W)), -32768, 32767)
+    out = []
+    for _ in range(n_each):
+        out.append(g(int(rng.integers(-30000, 30000)), 400))        # band
+        out.append(g(0, float(rng.choice([1, 30, 2000]))))          # band
+        t = g(0, 400)
+        idx = rng.random(W) < 0.01
+        t[idx] = np.clip(50 * 400 * rng.standard_t(2, int(idx.sum())), -32768, 32767)
+        out.append(t)                                               # band, Student-t bursts
+        out.append(g(0, float(rng.choice([3000, 12000]))))          # MAD past the band
+        out.append(rng.integers(-32768, 32768, W))                  # uniform
+        out.append(np.where(rng.random(W) < 0.5, -25000, 25000))    # bimodal
+        t = g(0, 400)
+        t[int(rng.integers(1, 4)) * 2048:] += int(rng.integers(5000, 20000))
+        out.append(np.clip(t, -32768, 32767))                       # level step
+        out.append(g(32700, 50))                                    # band clipped at the top
+        out.append(g(-32700, 50))                                   # band clipped at the bottom
+    return np.concatenate(out).astype(np.int16)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_w8192_band_and_radix_paths(gpu, mode):
+    """Every window kind through the W 8192 tile, both selection paths,
+    equal to the oracle in samples and statistics."""
+    rng = np.random.default_rng(31 + mode)
+    s = _band_and_radix_windows(rng)
+    x = synth.pack([torch.as_tensor(s), torch.as_tensor(s[::-1].copy())])
+    specs = [synth.StreamSpec(len(s), 8192, k, mode, 1, 0, 1, 1, "i16") for k in (3.0, 2.0)]
+    for sched in ("split", "fused"):
+        y, st = gpu_run(x, specs, 12, gpu, schedule=sched)
+        check_against_oracle(x, specs, 12, y, st)
+
+
 def test_all_schedules(gpu):
     specs = [synth.StreamSpec(8192 * 3 + 100, 8192, 3.0, rfi.NOISE, 400.0, 0.01, 32, 32, "i16"),
              synth.StreamSpec(9000, 2000, 2.5, rfi.CLIP, 200.0, 0.01, 32, 32, "i16")]
