@@ -392,8 +392,7 @@ struct I8TileSmem {
     static constexpr int kHistWords = kWide ? 4 * kWaveHistWords : (kWin / kRounds) * kNarrowStride;
     static_assert(kHistWords >= kNoiseAliasWords, "noise scratch aliases the histograms");
     __align__(16) uint32_t hist[kHistWords];
-    uint32_t tot[kWPW > 1 ? kWin * 256 : 0];
-    uint32_t pc[kWPW > 1 ? kWin * kPadC : 0];
+    __align__(16) uint32_t tot[kWPW > 1 ? 4 * 256 : 0];  // each wave's bin totals
     WinParams prm[kWin];
     int32_t mad[kWin];  // statistics-only mode: each window's MAD
     uint32_t noise_counts[NS ? 4 : 0];
@@ -507,11 +506,7 @@ __device__ __forceinline__ TileStats i8_tile(const StreamView& d, int64_t first,
         constexpr int WPW = Smem::kWPW;
         const int wl = wave / WPW;
         uint32_t* h = sm.hist + wave * kWaveHistWords;
-        if constexpr (WPW > 1) {
-            __syncthreads();  // the previous tile is done with tot, pc and prm
-            if (threadIdx.x < Smem::kWin * 64)
-                reinterpret_cast<uint4*>(sm.tot)[threadIdx.x] = make_uint4(0, 0, 0, 0);
-        }
+        if constexpr (WPW > 1) __syncthreads();  // the previous tile is done with tot and prm
         wide_hist_zero(h);
         wave_sync();
         uint32_t* hl = h + (lane & 3) * kRepStride;
@@ -523,30 +518,45 @@ __device__ __forceinline__ TileStats i8_tile(const StreamView& d, int64_t first,
         wave_sync();
         uint32_t c[4];
         wide_hist_totals(h, c);
-        // W = 4096: the cumulative counts overwrite replica 0 of this wave,
+        // The cumulative counts overwrite replica 0 of the selecting wave,
         // whose reads were all issued above.
-        uint32_t* pc = WPW == 1 ? h : sm.pc + wl * kPadC;
+        uint32_t* pc = h;
         int mb = 0, D = 0;
-        if constexpr (WPW == 1) {
-            wide_select(c, pc, need, mb, D);
-        } else {
-            __syncthreads();  // tot is zero everywhere
-#pragma unroll
-            for (int j = 0; j < 4; ++j) atomicAdd(&sm.tot[wl * 256 + lane * 4 + j], c[j]);
+        WinParams p;
+        rfi_window_stats ws;
+        if constexpr (WPW == 2) {
+            // W 8192: both waves publish their totals; after one barrier each
+            // wave adds its window's two and selects by itself (the same
+            // values in both, no second exchange).
+            *reinterpret_cast<uint4*>(sm.tot + wave * 256 + lane * 4) = make_uint4(c[0], c[1], c[2], c[3]);
             __syncthreads();
-            if (wave % WPW == 0) {
-                const uint4 t = *reinterpret_cast<const uint4*>(sm.tot + wl * 256 + lane * 4);
+            const uint4 t0 = *reinterpret_cast<const uint4*>(sm.tot + (wl * 2) * 256 + lane * 4);
+            const uint4 t1 = *reinterpret_cast<const uint4*>(sm.tot + (wl * 2 + 1) * 256 + lane * 4);
+            c[0] = t0.x + t1.x;
+            c[1] = t0.y + t1.y;
+            c[2] = t0.z + t1.z;
+            c[3] = t0.w + t1.w;
+        } else if constexpr (WPW == 4) {
+            // W 16384: the four waves' totals are added in LDS and one wave
+            // selects (selecting in all four measured slower).
+            if (threadIdx.x < 64) reinterpret_cast<uint4*>(sm.tot)[threadIdx.x] = make_uint4(0, 0, 0, 0);
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < 4; ++j) atomicAdd(&sm.tot[lane * 4 + j], c[j]);
+            __syncthreads();
+            if (wave == 0) {
+                const uint4 t = *reinterpret_cast<const uint4*>(sm.tot + lane * 4);
                 c[0] = t.x;
                 c[1] = t.y;
                 c[2] = t.z;
                 c[3] = t.w;
-                wide_select(c, pc, need, mb, D);
             }
         }
-        WinParams p;
-        if (wave % WPW == 0) {
-            rfi_window_stats ws;
+        if (WPW < 4 || wave == 0) {
+            wide_select(c, pc, need, mb, D);
             wide_params(pc, mb, D, d.k, W, p, ws);
+        }
+        if (wave % WPW == 0) {
             if (lane == 0) {
                 sm.prm[wl] = p;
                 if constexpr (MODE == kModeStats) sm.mad[wl] = D;
@@ -554,9 +564,9 @@ __device__ __forceinline__ TileStats i8_tile(const StreamView& d, int64_t first,
             ts.s = ws;
             ts.dst = (lane == 0 && d.stats) ? d.stats + first / W + wl : nullptr;
         }
-        if constexpr (WPW > 1) {
+        if constexpr (WPW == 4) {
             __syncthreads();
-            p = sm.prm[wl];
+            p = sm.prm[0];
         }
         if constexpr (MODE != kModeStats) i8_replace<W, NS, MODE>(d, first, seed, sm, v, [&](int) { return p; });
     } else {
