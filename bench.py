@@ -328,7 +328,9 @@ def bench_batching(args, dev):
                                                                "fused_persist", True),
                 ("batched_split_graph", "split", True),
                 ("batched_split_concurrent_graph", "split_concurrent", True),
-                ("batched_fused_concurrent_graph", "fused_concurrent", True)]
+                ("batched_fused_concurrent_graph", "fused_concurrent", True),
+                ("batched_one_launch_graph", "one_launch", True),
+                ("batched_one_launch_persist_graph", "one_launch_persist", True)]
     with torch.cuda.stream(stream):
         for name, sched, graph in variants:
             p = rfi.Plan(1, L, W, K, M, seed=3)

@@ -1616,6 +1616,27 @@ union I8FusedSmem {
     GenericSmem g;
 };
 
+// Generic items of the all-modes fused kernel, which is too large for the
+// compiler to inline the generic path: out of line, taking the descriptor's
+// address and the launch's base addresses as scalars and resolving the
+// stream itself.  Handing over the resolved stream (by reference, or by
+// value, which the calling convention also passes through memory) made
+// the caller store it to private memory before every item, tiles included:
+// about 5 KiB of writes per wave.
+template <bool REG, class Smem>
+__device__ __noinline__ void i8_generic_item(const StreamDesc* sd, uint64_t x_base, uint64_t y_base,
+                                             uint64_t stats_base, int32_t no_stats, int64_t w, uint64_t seed,
+                                             Smem& sm)
+{
+    LaunchArgs la;
+    la.x_base = x_base;
+    la.y_base = y_base;
+    la.stats_base = stats_base;
+    la.no_stats = no_stats;
+    const StreamView d = resolve(*sd, la);
+    i8_generic<REG>(d, w, seed, sm);
+}
+
 // Every item kind and window class in one launch.  MODES: the modes of the
 // launch's tiles (a kernel compiled for one mode needs fewer registers than
 // one that branches over all three, and registers bound its occupancy);
@@ -1627,6 +1648,13 @@ __global__ __launch_bounds__(kBlock) void k_i8_fused(LaunchArgs a)
     __shared__ I8FusedSmem<NS> sm;
     for_items<PERSIST>(a, [&](int64_t it) {
         const Item item = a.items[it];
+        if constexpr (MODES == 7) {
+            if (item.kind == kItemGeneric) {
+                i8_generic_item<true>(a.streams + item.stream, a.x_base, a.y_base, a.stats_base, a.no_stats,
+                                      item.first, a.seed, sm.g);
+                return;
+            }
+        }
         const StreamView d = resolve(a.streams[item.stream], a);
         if (item.kind == kItemGeneric) {
             i8_generic<(MODES & 3) != 0>(d, item.first, a.seed, sm.g);
