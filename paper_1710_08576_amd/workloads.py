@@ -12,6 +12,13 @@ Usage:  python -m paper_1710_08576_amd.workloads --workload plain --window 4096
             --modes zero,clip,noise --reps 5 --with-copy
         python -m paper_1710_08576_amd.workloads --workload int16 --reps 5
         python -m paper_1710_08576_amd.workloads --workload batching --schedule fused --reps 5
+        python -m paper_1710_08576_amd.workloads --workload batching --autotune-save tune.json
+        python -m paper_1710_08576_amd.workloads --workload batching --tune-file tune.json --reps 5
+
+--autotune-save tunes the workload's plan (every schedule timed on its
+buffers), writes the autotune table and exits; --tune-file loads such a
+table first, so that a later process (a profiled one) runs the tuned
+launches alone.
 """
 from __future__ import annotations
 
@@ -42,6 +49,8 @@ def main(argv=None):
     ap.add_argument("--schedule", default="auto")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--with-copy", action="store_true")
+    ap.add_argument("--autotune-save", default=None)
+    ap.add_argument("--tune-file", default=None)
     a = ap.parse_args(argv)
 
     import torch
@@ -50,6 +59,8 @@ def main(argv=None):
     from paper_1710_08576_amd import synth
     dev = torch.device("cuda:0")
     rfi.load()
+    if a.tune_file:
+        rfi.tune_load(a.tune_file)
     stream = torch.cuda.current_stream()
     out = {"workload": a.workload}
     if a.workload == "plain":
@@ -77,6 +88,16 @@ def main(argv=None):
     nw = rfi.layout(L, W)[2]
     st = torch.empty((nw, 4), dtype=torch.int32, device=dev)
     out["config"] = tag
+    if a.autotune_save:
+        inv = {v: k for k, v in rfi.SCHEDULES.items()}
+        for name, K, M in runs:
+            p = rfi.Plan(elem, L, W, K, M, seed=seed)
+            best, ms = p.autotune(x, y, st, iters=5, stream=stream)
+            out[name] = {"autotuned": inv.get(best, best), "ms": round(ms, 4)}
+            p.close()
+        rfi.tune_save(a.autotune_save)
+        print(json.dumps(out), flush=True)
+        return
     for name, K, M in runs:
         p = rfi.Plan(elem, L, W, K, M, seed=seed)
         if a.schedule != "auto":
