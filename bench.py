@@ -200,38 +200,37 @@ def main():
             rfi._lib.ubench_copy(x, y, 1)
         torch.cuda.synchronize()
 
-    # W = 16384 variant of the same workload (context, not the headline).
-    if not args.no_extra:
-        st16, plans16, nw16 = setup(16384)
-        run_steps(plans16, x, y, st16, 2)
+    # Other windows of the same workload (context, not the headline): each
+    # plan warmed like the headline's, then timed per launch; median and mean
+    # both reported (a rare stall on the box moves the mean only).
+    def side_window(window):
+        stw, plansw, nww = setup(window)
+        run_steps(plansw, x, y, stw, args.warmup)
         torch.cuda.synchronize()
-        ev16 = {m: ([], []) for m in (0, 1, 2)}
-        run_steps(plans16, x, y, st16, max(5, args.steps // 5), ev16)
+        evw = {m: ([], []) for m in (0, 1, 2)}
+        run_steps(plansw, x, y, stw, max(10, args.steps // 2), evw)
         torch.cuda.synchronize()
-        ms16 = {MODE_NAMES[m]: float(np.mean([a.elapsed_time(b) for a, b in zip(*ev16[m])]))
-                for m in (0, 1, 2)}
-        out["window_16384"] = {k: {"ms": round(v, 4), "gsamples_s": round(n_samples / v / 1e6, 1)}
-                               for k, v in ms16.items()}
-        for p in plans16.values():
+        abw = algorithmic_bytes(n_samples, nww)
+        res = {}
+        for m in (0, 1, 2):
+            t = [a.elapsed_time(b) for a, b in zip(*evw[m])]
+            v = float(np.median(t))
+            res[MODE_NAMES[m]] = {
+                "ms_median": round(v, 4), "ms": round(float(np.mean(t)), 4),
+                "gsamples_s": round(n_samples / v / 1e6, 1), "gb_s": round(abw / v / 1e6, 1),
+                "roofline_frac": round(abw / v / 1e6 / HBM_PEAK_GBS, 4),
+                "launches": plansw[m].info()["launches"]}
+        res["schedule"] = plansw[0].schedule()
+        for p in plansw.values():
             p.close()
+        del stw
+        return res
+
+    if not args.no_extra:
+        out["window_16384"] = side_window(16384)
         # W = 5000, not a tile class: every window through the generic
         # kernel (register-resident, one window per workgroup).
-        st5, plans5, nw5 = setup(5000)
-        run_steps(plans5, x, y, st5, 2)
-        torch.cuda.synchronize()
-        ev5 = {m: ([], []) for m in (0, 1, 2)}
-        run_steps(plans5, x, y, st5, max(5, args.steps // 5), ev5)
-        torch.cuda.synchronize()
-        ab5 = algorithmic_bytes(n_samples, nw5)
-        out["window_5000_generic"] = {}
-        for m in (0, 1, 2):
-            v = float(np.median([a.elapsed_time(b) for a, b in zip(*ev5[m])]))
-            out["window_5000_generic"][MODE_NAMES[m]] = {
-                "ms": round(v, 4), "gsamples_s": round(n_samples / v / 1e6, 1),
-                "gb_s": round(ab5 / v / 1e6, 1), "roofline_frac": round(ab5 / v / 1e6 / HBM_PEAK_GBS, 4)}
-        for p in plans5.values():
-            p.close()
-        del st5
+        out["window_5000_generic"] = side_window(5000)
 
     if not args.no_batching:
         out["batching"] = bench_batching(args, dev)
@@ -371,17 +370,24 @@ def bench_int16(args, dev):
     y = torch.empty_like(x)
     nw = rfi.layout(L, [8192] * len(L))[2]
     st = torch.empty((nw, 4), dtype=torch.int32, device=dev)
-    p = rfi.Plan(2, L, [8192] * len(L), [3.0] * len(L), [2] * len(L), seed=5)
     stream = torch.cuda.current_stream()
-    for _ in range(3):
-        p.execute(x, y, st, stream=stream)
-    ms = _time_events(lambda: p.execute(x, y, st, stream=stream), max(10, args.steps // 2), stream)
     n = sum(L)
     ab = algorithmic_bytes(n, nw, elem=2)
-    p.close()
-    return {"workload": "60 x 2^23 int16, window 8192, k 3, noise", "ms": round(ms, 4),
-            "gsamples_s": round(n / ms / 1e6, 1), "gb_s": round(ab / ms / 1e6, 1),
-            "roofline_frac": round(ab / ms / 1e6 / HBM_PEAK_GBS, 4)}
+    res = {"workload": "60 x 2^23 int16, window 8192, k 3, noise"}
+    # noise is the workload; zero and clip of the same batch for context
+    for m in (2, 0, 1):
+        p = rfi.Plan(2, L, [8192] * len(L), [3.0] * len(L), [m] * len(L), seed=5)
+        for _ in range(max(3, args.warmup)):
+            p.execute(x, y, st, stream=stream)
+        ms = _time_events(lambda: p.execute(x, y, st, stream=stream), max(10, args.steps // 2), stream)
+        r = {"ms": round(ms, 4), "gsamples_s": round(n / ms / 1e6, 1), "gb_s": round(ab / ms / 1e6, 1),
+             "roofline_frac": round(ab / ms / 1e6 / HBM_PEAK_GBS, 4)}
+        p.close()
+        if m == 2:
+            res.update(r)
+        else:
+            res.setdefault("other_modes", {})[MODE_NAMES[m]] = r
+    return res
 
 
 def bench_multi(args, dev, x, L):
