@@ -1640,9 +1640,14 @@ __device__ __noinline__ void i8_generic_item(const StreamDesc* sd, uint64_t x_ba
 // Every item kind and window class in one launch.  MODES: the modes of the
 // launch's tiles (a kernel compiled for one mode needs fewer registers than
 // one that branches over all three, and registers bound its occupancy);
-// generic items take any mode.
+// generic items take any mode.  The all-modes instance is bounded to four
+// workgroups per CU (120 VGPRs and a few spilled, against 132 and three
+// workgroups unbounded): on the 64-stream mixed batch 0.232 -> 0.214 ms in
+// one launch; five workgroups (96 VGPRs) spilled more and lost it again.
+// The one-mode instances keep the unbounded budget, which measured faster
+// than five or seven workgroups per CU.
 template <bool PERSIST, int MODES>
-__global__ __launch_bounds__(kBlock) void k_i8_fused(LaunchArgs a)
+__global__ __launch_bounds__(kBlock, MODES == 7 ? 4 : 0) void k_i8_fused(LaunchArgs a)
 {
     constexpr bool NS = (MODES & 4) != 0;
     __shared__ I8FusedSmem<NS> sm;
