@@ -136,6 +136,12 @@ hipError_t launch_i8_fused(int modes, const LaunchArgs& a, int grid, hipStream_t
 hipError_t launch_i16_tiles(int cls, int modes, const LaunchArgs& a, int grid, hipStream_t s);
 hipError_t launch_i16_generic(const LaunchArgs& a, int grid, hipStream_t s);
 hipError_t launch_i16_fused(const LaunchArgs& a, int grid, hipStream_t s);
+// One workgroup of the all-modes fused kernel (int8) or of the int16 fused
+// kernel with no items.  A kernel that needs private (scratch) memory has
+// it set up by the runtime at its first dispatch on a hardware queue, which
+// can hold that queue for milliseconds; a server runs this once per lane
+// when it is created, so that no block's latency pays for it.
+hipError_t warm_fused(int elem_size, bool persist, hipStream_t s);
 
 // Several outputs from one read (int8 tile items): output o uses the
 // descriptors desc[o] (its k and mode; offsets as a.streams) and the bases

@@ -2254,6 +2254,15 @@ hipError_t launch_i16_fused(const LaunchArgs& a, int grid, hipStream_t s)
 }
 #undef RFI_PICK
 
+hipError_t warm_fused(int elem_size, bool persist, hipStream_t s)
+{
+    LaunchArgs a{};  // no items: the workgroup returns at once
+    void (*k)(LaunchArgs) = elem_size == 1 ? (persist ? i8_fused_kernel<true>(7) : i8_fused_kernel<false>(7))
+                                           : (persist ? k_i16_fused<true> : k_i16_fused<false>);
+    void* kargs[] = {&a};
+    return hipLaunchKernel(reinterpret_cast<const void*>(k), dim3(1), dim3(kBlock), kargs, 0, s);
+}
+
 __global__ __launch_bounds__(kBlock) void k_mom_apply(LaunchArgs a, const MomItem* __restrict__ items,
                                                       const int32_t* __restrict__ dm,
                                                       const int64_t* __restrict__ stream_woff,

@@ -577,6 +577,11 @@ int rfi_server_create(const rfi_server_config* cfg, rfi_server** out)
             // Growing a slot later synchronises the device; start large.
             if (e == hipSuccess) rc = ensure_slot(L.slots[s], kSlotPrealloc);
         }
+        // The batch kernels this lane will launch, once, with no items.
+        if (e == hipSuccess && rc == RFI_OK) e = warm_fused(cfg->elem_size, false, L.s);
+        if (e == hipSuccess && rc == RFI_OK && cfg->schedule == RFI_SCHED_FUSED_PERSIST)
+            e = warm_fused(cfg->elem_size, true, L.s);
+        if (e == hipSuccess && rc == RFI_OK) e = hipStreamSynchronize(L.s);
         if (e != hipSuccess || rc != RFI_OK) {
             rfi_server_destroy(srv);
             return e != hipSuccess ? hip_fail(e) : rc;
