@@ -307,13 +307,15 @@ template <int P> struct NoisePart;
 template <> struct NoisePart<4> { using T = uint32_t; };
 template <> struct NoisePart<2> { using T = uint2; };
 
-template <int P, class PartFn>
+// NT: threads of the workgroup (a multiple of 64, at most 256); the list
+// holds NT parts a round.
+template <int P, int NT = kBlock, class PartFn>
 __device__ __forceinline__ void pool_noise(uint32_t (&v)[16], uint32_t cf, const NoiseScratch& ns,
                                            PartFn merged)
 {
     using PartT = typename NoisePart<P>::T;
     constexpr int WPP = 4 / P;  // dwords per part
-    constexpr int C = kBlock;   // parts per round
+    constexpr int C = NT;       // parts per round
     PartT* data = reinterpret_cast<PartT*>(ns.data);
     const int lane = lane_id();
     const int wave = (int)(threadIdx.x >> 6);
@@ -323,7 +325,7 @@ __device__ __forceinline__ void pool_noise(uint32_t (&v)[16], uint32_t cf, const
     __syncthreads();
     int wbase = 0, F = 0;
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
+    for (int w = 0; w < NT / 64; ++w) {
         const int c = (int)ns.counts[w];
         wbase += w < wave ? c : 0;
         F += c;
@@ -822,24 +824,43 @@ __device__ void i8_generic_reg(const StreamView& d, int64_t w, int64_t a, int n,
     bool noise = false;
     if constexpr (NOISE) {
         if (d.mode == RFI_MODE_NOISE) {
-            // One Philox block per dword holding a flagged sample, drawn in a
-            // loop over this lane's flagged dwords (one inlined draw).
+            // One Philox block per dword holding a flagged sample (dword q
+            // of a lane: chunk tid + (q / 4) NT, samples 4 (q % 4) ..), the
+            // flagged dwords of the workgroup pooled so that the draws take
+            // as few waves as there are flagged dwords.  The histograms are
+            // dead once every wave holds the window's parameters.
             noise = true;
             uint32_t cf = 0;
 #pragma unroll
             for (int q = 0; q < 16; ++q)
                 if (tid + (q >> 2) * NT < nch) cf |= ((clamp_i8x4(v[q], lo, hi) ^ v[q]) != 0 ? 1u : 0u) << q;
-            while (cf) {
-                const int q = __builtin_ctz(cf);
-                cf &= cf - 1;
-                uint32_t x = 0;
+            const int64_t jb = d.abs_base + c0 * 16;
+            if constexpr (NT >= 128) {
+                auto merged = [&](int wv, int ln, int slot, int part, uint32_t x) -> uint32_t {
+                    const int64_t j0 = jb + ((int64_t)(wv * 64 + ln) + (int64_t)slot * NT) * 16 + 4 * part;
+                    const uint32_t nz = noise_quad_i8((uint64_t)j0, seed, d.key, p.m, p.sq8);
+                    return byte_perm(nz, x, flag_sel_i8x4(x, lo_u, hi_u));
+                };
+                static_assert(sizeof(sm.whist) >= (16 + 2 * NT) * 4, "noise list in the histograms");
+                pool_noise<4, NT>(v, cf,
+                                  NoiseScratch{sm.whist, sm.whist + 16, reinterpret_cast<uint4*>(sm.whist + 16 + NT)},
+                                  merged);
+            } else {
+                // One-wave workgroups (windows of at most 256 chunks) hold
+                // few flagged dwords: each lane draws its own, in a loop over
+                // them (no list, no barriers, fewer registers).
+                while (cf) {
+                    const int q = __builtin_ctz(cf);
+                    cf &= cf - 1;
+                    uint32_t x = 0;
 #pragma unroll
-                for (int i = 0; i < 16; ++i) x = i == q ? v[i] : x;
-                const int64_t j0 = d.abs_base + (c0 + tid + (int64_t)(q >> 2) * NT) * 16 + 4 * (q & 3);
-                const uint32_t nz = noise_quad_i8((uint64_t)j0, seed, d.key, p.m, p.sq8);
-                x = byte_perm(nz, x, flag_sel_i8x4(x, lo_u, hi_u));
+                    for (int i = 0; i < 16; ++i) x = i == q ? v[i] : x;
+                    const int64_t j0 = jb + (tid + (int64_t)(q >> 2) * NT) * 16 + 4 * (q & 3);
+                    const uint32_t nz = noise_quad_i8((uint64_t)j0, seed, d.key, p.m, p.sq8);
+                    x = byte_perm(nz, x, flag_sel_i8x4(x, lo_u, hi_u));
 #pragma unroll
-                for (int i = 0; i < 16; ++i) v[i] = i == q ? x : v[i];
+                    for (int i = 0; i < 16; ++i) v[i] = i == q ? x : v[i];
+                }
             }
         }
     }
@@ -1582,7 +1603,7 @@ __global__ __launch_bounds__(kBlock) void k_i8_tiles(LaunchArgs a)
 // windows in flight per CU instead of the 8 of the 256-thread kernel.  One
 // item per workgroup.
 template <int NT, bool NOISE>
-__global__ __launch_bounds__(NT) void k_i8_generic_small(LaunchArgs a)
+__global__ __launch_bounds__(NT, NOISE && NT >= 128 ? 8 : 0) void k_i8_generic_small(LaunchArgs a)
 {
     __shared__ GenericSmemN<NT / 64> sm;
     if ((int64_t)blockIdx.x >= a.n_items) return;
@@ -1595,7 +1616,7 @@ __global__ __launch_bounds__(NT) void k_i8_generic_small(LaunchArgs a)
 // that include noise streams: the draw costs registers the other modes'
 // small windows would pay for in occupancy).
 template <bool PERSIST, bool NOISE>
-__global__ __launch_bounds__(kBlock) void k_i8_generic(LaunchArgs a)
+__global__ __launch_bounds__(kBlock, NOISE ? (PERSIST ? 4 : 8) : 0) void k_i8_generic(LaunchArgs a)
 {
     __shared__ GenericSmem sm;
     for_items<PERSIST>(a, [&](int64_t it) {
