@@ -1367,7 +1367,6 @@ __device__ void i16_tile_8192(const StreamView& d, int64_t first, uint64_t seed,
     const int tid = (int)threadIdx.x;
     const int wbase = (tid >> 6) * 4096;  // bytes
     const uint8_t* xt = reinterpret_cast<const uint8_t*>(static_cast<const int16_t*>(d.x) + first) + wbase + lane * 16;
-    uint8_t* yt = reinterpret_cast<uint8_t*>(static_cast<int16_t*>(d.y) + first) + wbase + lane * 16;
 
     uint32_t v[16];
 #pragma unroll
@@ -1424,6 +1423,12 @@ __device__ void i16_tile_8192(const StreamView& d, int64_t first, uint64_t seed,
         };
         pool_noise<2>(v, cf, sm.noise(), merged);
     }
+    // The store address is formed here from a fresh copy of the thread
+    // index: kept live from the loads, its lane and wave offsets were spilled
+    // to private memory and reloaded right before the stores.
+    uint32_t t2 = (uint32_t)tid;
+    asm volatile("" : "+v"(t2));
+    uint8_t* yt = reinterpret_cast<uint8_t*>(static_cast<int16_t*>(d.y) + first) + (t2 >> 6) * 4096 + (t2 & 63) * 16;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
         gstore16_nt(yt + i * 1024, make_uint4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]));
