@@ -570,6 +570,10 @@ __device__ __forceinline__ TileStats i8_tile(const StreamView& d, int64_t first,
             __syncthreads();
             p = sm.prm[0];
         }
+        // The record is complete: write it now rather than keep it in
+        // registers through the replacement (the noise draws' peak).
+        write_stats(ts);
+        ts.dst = nullptr;
         if constexpr (MODE != kModeStats) i8_replace<W, NS, MODE>(d, first, seed, sm, v, [&](int) { return p; });
     } else {
         // Several windows per wave: one 256-bin histogram of x + 128 per
@@ -647,6 +651,8 @@ __device__ __forceinline__ TileStats i8_tile(const StreamView& d, int64_t first,
             }
         }
         wave_sync();
+        write_stats(ts);
+        ts.dst = nullptr;
         if constexpr (MODE != kModeStats)
             i8_replace<W, NS, MODE>(d, first, seed, sm, v, [&](int i) {
                 return sm.prm[(wbase + i * 1024 + lane * 16) / W];
