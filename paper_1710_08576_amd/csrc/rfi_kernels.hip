@@ -1673,9 +1673,11 @@ __device__ __noinline__ void i8_generic_item(const StreamDesc* sd, uint64_t x_ba
 // launch's tiles (a kernel compiled for one mode needs fewer registers than
 // one that branches over all three, and registers bound its occupancy);
 // generic items take any mode.  The all-modes instance is bounded to four
-// workgroups per CU (120 VGPRs and a few spilled, against 132 and three
-// workgroups unbounded): on the 64-stream mixed batch 0.232 -> 0.214 ms in
-// one launch; five workgroups (96 VGPRs) spilled more and lost it again.
+// workgroups per CU (120 VGPRs, against 132 and three workgroups unbounded,
+// a count set by the out-of-line generic item, which under the bound saves
+// four callee-saved registers to private memory): on the 64-stream mixed
+// batch 0.232 -> 0.214 ms in one launch; five workgroups (96 VGPRs)
+// spilled in the tile code and lost it again.
 // The one-mode instances keep the unbounded budget, which measured faster
 // than five or seven workgroups per CU.
 template <bool PERSIST, int MODES>

@@ -39,11 +39,38 @@ KERNEL_SOURCES = ["csrc/rfi_kernels.hip", "csrc/rfi_device.hpp", "csrc/rfi_inter
                   "csrc/q8_table.inc"]
 
 
-def kernel_source_hash() -> str:
+def _code_only(text: str) -> str:
+    """The source with its comments removed and whitespace collapsed."""
+    out = []
+    i, n = 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
+def kernel_source_hash(root: str = HERE) -> str:
+    """sha256 of the kernel sources' code: comments and layout do not count,
+    so a profile stays valid across an edit of comments alone."""
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(HERE, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(root, rel), encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()
 
 

@@ -162,3 +162,23 @@ def test_tune_table_json_round_trip(tmp_path):
             rfi.tune_load(str(f))
     with pytest.raises(rfi.RfiError):
         rfi.tune_load(str(tmp_path / "missing.json"))
+
+
+def test_kernel_source_hash_ignores_comments(tmp_path):
+    # the hash that ties a profile to the kernels it was taken on changes
+    # with the code and not with comments or layout
+    import shutil
+    from paper_1710_08576_amd import profiling
+    for rel in profiling.KERNEL_SOURCES:
+        dst = tmp_path / rel
+        dst.parent.mkdir(parents=True, exist_ok=True)
+        shutil.copy(os.path.join(profiling.HERE, rel), dst)
+    h0 = profiling.kernel_source_hash(str(tmp_path))
+    assert h0 == profiling.kernel_source_hash()
+    k = tmp_path / "csrc" / "rfi_kernels.hip"
+    text = k.read_text()
+    k.write_text("// a new comment\n/* and a block\n   comment */\n" + text.replace("\n", "\n\n", 3))
+    assert profiling.kernel_source_hash(str(tmp_path)) == h0
+    d = tmp_path / "csrc" / "rfi_device.hpp"
+    d.write_text(d.read_text() + "\nstatic const int extra_code = 1;\n")
+    assert profiling.kernel_source_hash(str(tmp_path)) != h0
