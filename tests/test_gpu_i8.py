@@ -86,6 +86,19 @@ def test_threshold_multiples(gpu, k):
     check_against_oracle(x, specs, 2, y, st)
 
 
+@pytest.mark.parametrize("k", [0.0, 0.5, 2.0])
+def test_generic_noise_many_flagged(gpu, k):
+    """Noise windows of the generic path with most samples flagged: the
+    pooled draws of 128- and 256-thread workgroups (W 5000, 12000) take
+    several rounds of the list, the 64-thread ones (W 3000) loop in the
+    lane; equal to the oracle in every split and fused schedule."""
+    specs = [synth.StreamSpec(W * 3 + 77, W, k, rfi.NOISE, 12.0, 0.02, 8, 512) for W in (3000, 5000, 12000)]
+    x = synth.gen_packed(specs, seed=int(k * 10) + 1, tag=31)
+    for sched in ("split", "split_persist", "fused"):
+        y, st = gpu_run(x, specs, 4, gpu, schedule=sched)
+        check_against_oracle(x, specs, 4, y, st)
+
+
 def test_mixed_batch_all_schedules_and_graphs(gpu):
     """Uneven streams with per-stream W, k, mode; every schedule and HIP-graph
     replay give the same bytes as the oracle."""
