@@ -261,3 +261,29 @@ def test_large_carry_equals_whole_stream(gpu, mom_k):
                                st_ref[s * 3 * nwc + c * nwc:s * 3 * nwc + (c + 1) * nwc]), (c, s)
     torch.cuda.synchronize()
     assert hlen.cpu().tolist() == [mom_k - 1] * ns
+
+
+@pytest.mark.parametrize("carry", [False, True])
+def test_large_batch_with_empty_streams(gpu, carry):
+    # a 70 M-sample stream followed by empty ones: the batch is cut into
+    # chunks of whole streams, three of which hold no window; the result
+    # equals the oracle, with and without a carried history
+    W, K = 4096, 300
+    L = [70_000_000, 0, 0, 0]
+    specs = [synth.StreamSpec(max(l, 1), W, 3.0, 2, 9.0, 0.01, 8, 3000) for l in L]
+    xd = synth.gen_packed(specs[:1], 7, 45, device=gpu)
+    n = len(L)
+    if carry:
+        hist = torch.zeros((n, K - 1), dtype=torch.uint8, device=gpu)
+        hlen = torch.zeros(n, dtype=torch.int32, device=gpu)
+        absb = torch.zeros(n, dtype=torch.int64, device=gpu)
+        y, st = rfi.mom_filter_carry(xd, L, [W] * n, [3.0] * n, [2] * n, K, absb, hist, hlen, seed=4)
+    else:
+        y, st = rfi.mom_filter(xd, L, [W] * n, [3.0] * n, [2] * n, K, seed=4)
+    torch.cuda.synchronize()
+    xs = xd[:L[0]].cpu().numpy()
+    yo, sto = _oracle_stream(xs, 0, W, 3.0, 2, K, 4)
+    assert np.array_equal(y[:L[0]].cpu().numpy(), yo)
+    assert np.array_equal(rfi.stats_numpy(st), sto)
+    if carry:
+        assert hlen.cpu().tolist() == [K - 1, 0, 0, 0]
