@@ -42,8 +42,9 @@ _lib = None
 
 
 def default_threads() -> int:
-    """Host threads for the batch calls: all cores, at most 16 (a GPU machine
-    grants one GPU's share of its CPUs, whatever the core count shows)."""
+    """Host threads for the batch calls: all cores, at most 16 (a host
+    shared by several GPUs grants a process one GPU's share of its CPUs,
+    whatever the core count shows)."""
     return max(1, min(os.cpu_count() or 1, 16))
 
 
