@@ -1715,12 +1715,14 @@ __global__ __launch_bounds__(kBlock, MODES == 7 ? 4 : 0) void k_i8_fused(LaunchA
     });
 }
 
-// Eight workgroups per CU: the noise variant then holds 64 VGPRs (68
-// unbounded, 7 workgroups), with a few spilled registers; measured 2.8 %
-// faster in noise mode, unchanged in zero and clip.  (The int8 tiles,
-// bounded to 72 VGPRs the same way, measured 2-3 % slower in noise mode.)
+// One tile per workgroup: eight workgroups per CU (the noise variant holds
+// 63 VGPRs, against 68 and seven workgroups unbounded; 2.8 % faster in
+// noise mode, zero and clip unchanged).  The persistent loop keeps more
+// live (90-107 VGPRs): bounded the same way it spilled 88-120 bytes per
+// lane and ran 27-31 % slower, so it keeps the unbounded budget.  (The int8
+// tiles, bounded to 72 VGPRs, measured 2-3 % slower in noise mode.)
 template <bool PERSIST, int MODES>
-__global__ __launch_bounds__(kBlock, 8) void k_i16_tiles(LaunchArgs a)
+__global__ __launch_bounds__(kBlock, PERSIST ? 0 : 8) void k_i16_tiles(LaunchArgs a)
 {
     __shared__ I16TileSmem sm;
     for_items<PERSIST>(a, [&](int64_t it) {
