@@ -375,6 +375,70 @@ __device__ __forceinline__ void pool_noise(uint32_t (&v)[16], uint32_t cf, const
     }
 }
 
+// pool_noise without its first barrier: each wave reserves its slots with
+// one LDS atomic add on ns.counts[0], which the caller has zeroed before a
+// workgroup barrier that precedes the call (the waves' slots then follow
+// in the order of their adds).  The total is read after the barrier that
+// closes the list writes.
+template <int P, class PartFn>
+__device__ __forceinline__ void pool_noise_reserved(uint32_t (&v)[16], uint32_t cf, const NoiseScratch& ns,
+                                                    PartFn merged)
+{
+    using PartT = typename NoisePart<P>::T;
+    constexpr int WPP = 4 / P;
+    constexpr int C = kBlock;
+    PartT* data = reinterpret_cast<PartT*>(ns.data);
+    const int lane = lane_id();
+    const int wave = (int)(threadIdx.x >> 6);
+    const uint32_t cnt = __popc(cf);
+    const uint32_t incl = group_incl_scan<64>(cnt);
+    uint32_t wb = 0;
+    if (lane == 63 && incl) wb = atomicAdd(&ns.counts[0], incl);
+    wb = (uint32_t)__builtin_amdgcn_readlane((int)wb, 63);
+    const int base = (int)(wb + incl - cnt);
+    for (int r0 = 0;; r0 += C) {
+        int e = base - r0;
+#pragma unroll
+        for (int q = 0; q < 4 * P; ++q) {
+            if ((cf >> q) & 1u) {
+                if (e >= 0 && e < C) {
+                    ns.list[e] = (uint32_t)(wave << 8 | lane << 2 | (q / P)) | (uint32_t)(q % P) << 16;
+                    if constexpr (P == 4) data[e] = v[q];
+                    else data[e] = make_uint2(v[WPP * q], v[WPP * q + 1]);
+                }
+                ++e;
+            }
+        }
+        __syncthreads();
+        const int F = (int)ns.counts[0];  // every wave has added its count
+        const int k = (int)threadIdx.x;
+        if (k < min(C, F - r0)) {
+            const uint32_t ent = ns.list[k];
+            data[k] = merged((int)((ent >> 8) & 3u), (int)((ent >> 2) & 63u), (int)(ent & 3u),
+                             (int)(ent >> 16), data[k]);
+        }
+        __syncthreads();
+        e = base - r0;
+#pragma unroll
+        for (int q = 0; q < 4 * P; ++q) {
+            if ((cf >> q) & 1u) {
+                if (e >= 0 && e < C) {
+                    if constexpr (P == 4) {
+                        v[q] = data[e];
+                    } else {
+                        const uint2 t = data[e];
+                        v[WPP * q] = t.x;
+                        v[WPP * q + 1] = t.y;
+                    }
+                }
+                ++e;
+            }
+        }
+        __syncthreads();
+        if (r0 + C >= F) break;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // int8 tiles: 16 KiB of whole windows of one class W, 64 bytes per lane.
 // ---------------------------------------------------------------------------
@@ -1271,6 +1335,7 @@ __device__ bool i16_select_band(const uint32_t (&v)[16], I16TileSmem& sm, int& m
     if (tid == 0) {
         sm.below = 0;
         sm.flagged = 0;  // added to once the tile is replaced
+        sm.noise_counts[0] = 0;  // the noise pool's slot reservations
     }
     __syncthreads();
     uint32_t e[4] = {sm.est[0], sm.est[1], sm.est[2], sm.est[3]};
@@ -1427,7 +1492,7 @@ __device__ void i16_tile_8192(const StreamView& d, int64_t first, uint64_t seed,
             const uint32_t m1 = nonzero_half_mask(pk_clamp_i16(x.y, lo2, hi2) ^ x.y);
             return make_uint2((x.x & ~m0) | (nz.x & m0), (x.y & ~m1) | (nz.y & m1));
         };
-        pool_noise<2>(v, cf, sm.noise(), merged);
+        pool_noise_reserved<2>(v, cf, sm.noise(), merged);
     }
     // The store address is formed here from a fresh copy of the thread
     // index: kept live from the loads, its lane and wave offsets were spilled
