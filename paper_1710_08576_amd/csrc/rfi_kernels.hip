@@ -1325,10 +1325,11 @@ __device__ bool i16_select_band(const uint32_t (&v)[16], I16TileSmem& sm, int& m
     const uint32_t us = (pick ^ 0x8000u) & 0xFFFFu;
     uint32_t est = 0;
 #pragma unroll
-    for (int b = 15; b >= 0; --b) {
+    for (int b = 15; b >= 8; --b) {
         const uint32_t t = est | (1u << b);
         est = __popcll(__ballot(us < t)) < 32 ? t : est;
     }
+    est += 128;  // the middle of the 256-value bucket holding the estimate
     __syncthreads();  // the previous tile is done with the scratch
     zero_words(sm.h, kI16Band + 16, tid, kBlock);
     if (lane == 0) sm.est[wave] = est;
