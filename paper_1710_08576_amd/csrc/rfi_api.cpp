@@ -276,7 +276,10 @@ struct rfi_plan {
     std::vector<int32_t> M;
     std::vector<StreamDesc> hdesc;
     std::vector<Item> hitems;
-    std::vector<Item> hitems_fused;  // the same items, mode-major (fused launches)
+    // the same items twice: mode-major (fused launches), then from
+    // one_first in the single-launch order
+    std::vector<Item> hitems_fused;
+    int64_t one_first = 0;
     StreamDesc* ddesc = nullptr;
     Item* ditems = nullptr;
     Item* ditems_fused = nullptr;
@@ -394,7 +397,7 @@ static void build_launches(rfi_plan* p)
     // of that mode; int16 runs them all in one launch.
     {
         int64_t b = 0;
-        const int64_t nf = (int64_t)p->hitems_fused.size();
+        const int64_t nf = p->one_first;
         while (b < nf) {
             int64_t e = nf;
             int modes = 7;
@@ -411,15 +414,16 @@ static void build_launches(rfi_plan* p)
             b = e;
         }
     }
-    // One launch over every item of every class and mode (mode-major
-    // order), one workgroup per item or a persistent grid: the whole batch
-    // as a single kernel, compiled for the modes present.
+    // One launch over every item of every class and mode (in the
+    // heaviest-first order), one workgroup per item or a persistent grid:
+    // the whole batch as a single kernel, compiled for the modes present.
     {
-        const int64_t nf = (int64_t)p->hitems_fused.size();
+        const int64_t nf = (int64_t)p->hitems_fused.size() - p->one_first;
         if (nf > 0) {
             int modes = 0;
-            for (const Item& it : p->hitems_fused) modes |= 1 << p->M[it.stream];
-            PlanLaunch f{2, 0, -1, modes, 0, nf, clamp_grid(nf)};
+            for (int64_t i = p->one_first; i < p->one_first + nf; ++i)
+                modes |= 1 << p->M[p->hitems_fused[i].stream];
+            PlanLaunch f{2, 0, -1, modes, p->one_first, nf, clamp_grid(nf)};
             p->launches[RFI_SCHED_ONE_LAUNCH].push_back(f);
             f.grid = (int)std::min<int64_t>(nf, persistent_grid(elem, -1, modes, true));
             p->launches[RFI_SCHED_ONE_LAUNCH_PERSIST].push_back(f);
@@ -525,6 +529,23 @@ int plan_build(int elem, int32_t n, const int64_t* L, const int32_t* W, const fl
             p->hitems_fused.insert(p->hitems_fused.end(), g.begin(), g.end());
         }
     }
+    // The single-launch schedules take the same items in a second order,
+    // appended after the mode-major one: generic windows first, then the
+    // noise tiles, then the others, narrow classes first in each, so that
+    // a launch handing out items in order ends on its cheapest tiles.
+    p->one_first = (int64_t)p->hitems_fused.size();
+    for (int m : {RFI_MODE_NOISE, RFI_MODE_ZERO, RFI_MODE_CLIP})
+        for (const Item& it : groups[0])
+            if (M[it.stream] == m) p->hitems_fused.push_back(it);
+    for (int c = 0; c < ncls; ++c) {
+        const auto& g = groups[(c + 1) * kModes + RFI_MODE_NOISE];
+        p->hitems_fused.insert(p->hitems_fused.end(), g.begin(), g.end());
+    }
+    for (int c = 0; c < ncls; ++c)
+        for (int m : {RFI_MODE_ZERO, RFI_MODE_CLIP}) {
+            const auto& g = groups[(c + 1) * kModes + m];
+            p->hitems_fused.insert(p->hitems_fused.end(), g.begin(), g.end());
+        }
     if (n > 0) {
         hipError_t e = hipMalloc(&p->ddesc, sizeof(StreamDesc) * n);
         if (e != hipSuccess) return e == hipErrorOutOfMemory ? RFI_ERR_NOMEM : hip_fail(e);
