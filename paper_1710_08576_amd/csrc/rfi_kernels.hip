@@ -379,7 +379,10 @@ __device__ __forceinline__ void pool_noise(uint32_t (&v)[16], uint32_t cf, const
 // one LDS atomic add on ns.counts[0], which the caller has zeroed before a
 // workgroup barrier that precedes the call (the waves' slots then follow
 // in the order of their adds).  The total is read after the barrier that
-// closes the list writes.
+// closes the list writes.  A wave writes its list entries and parts as soon
+// as it arrives, so the list and the parts must have storage of their own:
+// unlike pool_noise's, they cannot alias memory that another wave of the
+// workgroup may still be reading.
 template <int P, class PartFn>
 __device__ __forceinline__ void pool_noise_reserved(uint32_t (&v)[16], uint32_t cf, const NoiseScratch& ns,
                                                     PartFn merged)
@@ -1119,10 +1122,15 @@ struct I16TileSmem {
     uint32_t mad_below;    // samples with |x - m| below the MAD bracket
     uint32_t est[4];       // band path: the waves' median estimates
     uint32_t below;        // band path: samples below the band
+    // The noise pool (pool_noise_reserved) writes its list while other
+    // waves may still be searching the band's counts in h, so it has
+    // storage of its own (3 KiB; 8 workgroups per CU still fit).
     uint32_t noise_counts[4];
+    __align__(16) uint32_t noise_list[256];
+    __align__(16) uint2 noise_data[256];
     __device__ NoiseScratch noise()
     {
-        return NoiseScratch{noise_counts, h, reinterpret_cast<uint4*>(h + 256)};
+        return NoiseScratch{noise_counts, noise_list, reinterpret_cast<uint4*>(noise_data)};
     }
 };
 
