@@ -35,6 +35,20 @@ def test_generic_windows(gpu, W, mode):
     check_against_oracle(x, specs, 6, y, st)
 
 
+@pytest.mark.parametrize("k", [0.0, 0.5, 1.0])
+def test_w8192_noise_many_flagged(gpu, k):
+    """W 8192 noise tiles with most samples flagged (a threshold of at most
+    one MAD): the tile's pool of flagged 4-sample parts runs several rounds
+    of its list (up to 2048 parts against 256 per round); equal to the
+    oracle in the one-class and fused launches."""
+    specs = [synth.StreamSpec(8192 * 3 + 211, 8192, k, rfi.NOISE, 400.0, 0.01, 32, 32, "i16"),
+             synth.StreamSpec(8192 * 2, 8192, k, rfi.NOISE, 30.0, 0.0, 1, 1, "i16")]
+    x = synth.gen_packed(specs, seed=int(k * 10) + 3, tag=24)
+    for sched in ("split", "split_persist", "fused"):
+        y, st = gpu_run(x, specs, 14, gpu, schedule=sched)
+        check_against_oracle(x, specs, 14, y, st)
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_degenerate(gpu, mode):
     rng = np.random.default_rng(2)

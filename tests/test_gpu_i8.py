@@ -86,6 +86,20 @@ def test_threshold_multiples(gpu, k):
     check_against_oracle(x, specs, 2, y, st)
 
 
+@pytest.mark.parametrize("k", [0.0, 0.5])
+def test_tile_noise_many_flagged(gpu, k):
+    """Noise tiles of every class with most samples flagged: each tile's
+    pool of flagged dwords runs several rounds of its list (up to 1024
+    dwords against 256 per round); equal to the oracle in the one-class,
+    fused and single launches."""
+    specs = [synth.StreamSpec(16384 * 2 + 300, W, k, rfi.NOISE, 12.0, 0.02, 8, 512)
+             for W in (512, 1024, 2048, 4096, 8192, 16384)]
+    x = synth.gen_packed(specs, seed=int(k * 10) + 5, tag=33)
+    for sched in ("split", "fused", "one_launch"):
+        y, st = gpu_run(x, specs, 6, gpu, schedule=sched)
+        check_against_oracle(x, specs, 6, y, st)
+
+
 @pytest.mark.parametrize("k", [0.0, 0.5, 2.0])
 def test_generic_noise_many_flagged(gpu, k):
     """Noise windows of the generic path with most samples flagged: the
