@@ -59,6 +59,19 @@ def test_mixed_batch(gpu, mom_k):
     _check(x, L, W, K, M, mom_k, 5, y, st)
 
 
+@pytest.mark.parametrize("k", [0.0, 0.5])
+def test_noise_many_flagged(gpu, k):
+    """Noise with most samples flagged (a threshold of at most one median of
+    MADs): the replacement's pool of flagged dwords runs several rounds of its
+    list in whole 16 KiB items (W 1024, 4096, 16384), and W 3000 draws sample
+    by sample; equal to the oracle."""
+    specs = [synth.StreamSpec(16384 * 3 + 500, W, k, rfi.NOISE, 12.0, 0.02, 8, 512)
+             for W in (1024, 4096, 16384, 3000)]
+    x, L, W, K, M = _batch(specs, 90 + int(k * 10))
+    y, st = _run(x, L, W, K, M, 5, 7, gpu)
+    _check(x, L, W, K, M, 5, 7, y, st)
+
+
 def test_k1_equals_plain_filter(gpu):
     specs = [synth.StreamSpec(4096 * 40, 4096, 3.0, m, 10.0, 0.01, 8, 500) for m in (0, 1, 2)]
     x, L, W, K, M = _batch(specs, 3)
